@@ -280,7 +280,8 @@ int oracle_join_plain(int64_t n, int64_t m, const int64_t* rp, const int32_t* co
 /*    stays below t form the unindexed part x', the rest are indexed    */
 /*    (a component is indexed as soon as b, including it, reaches t).   */
 /*    With l2_clause, the unindexed part also stops once its own L2     */
-/*    norm reaches t, which keeps dot(q, x') < t for any unit query q.  */
+/*    norm reaches t (compared as squared norm >= t*t, exact for a      */
+/*    float t), which keeps dot(q, x') < t for any unit query q.        */
 /* Outputs: rank[m] (position of each dim in the order), mw[m],         */
 /* cut[n] (number of unindexed components of each row).                */
 /* ------------------------------------------------------------------ */
@@ -336,7 +337,7 @@ int oracle_prefix_index(int64_t n, int64_t m, const int64_t* rp, const int32_t* 
         double w = (double)val[e];
         b += w * (double)mw[col[e]];
         sq += w * w;
-        if (b >= t || (l2_clause && sqrt(sq) >= t)) { c = (int32_t)k; break; }
+        if (b >= t || (l2_clause && sq >= t * t)) { c = (int32_t)k; break; }
       }
       cut[i] = c;
     }
