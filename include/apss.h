@@ -58,7 +58,9 @@ typedef struct {
   int32_t query_safe;    /* 1 (default): the unindexed part of every vector also stops once its
                             own L2 norm reaches t, so dot(q, x') < t for any unit query q and the
                             index answers apss_query; 0: the paper's cutoff only (join only) */
-  int32_t block_rows;    /* corpus rows per accumulator block (0 = default 2048; power of two) */
+  int32_t variant;       /* compiled tile variant of the join kernel (queries per tile x corpus
+                            rows per block); -1 = the library's default.  The environment
+                            variable APSS_VARIANT overrides it. */
   int32_t head_dims;     /* densest dimensions that get per-block list offsets (0 = default) */
   int32_t reserved[8];
 } apss_opts;

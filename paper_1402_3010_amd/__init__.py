@@ -39,7 +39,7 @@ class ApssError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("stream", ctypes.c_void_p), ("query_safe", ctypes.c_int32),
-                ("block_rows", ctypes.c_int32), ("head_dims", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("variant", ctypes.c_int32), ("head_dims", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
 
 
 class Pairs(ctypes.Structure):
@@ -149,12 +149,13 @@ def current_stream_handle() -> Optional[int]:
     return None
 
 
-def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0) -> Opts:
+def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, variant: int = -1) -> Opts:
     o = Opts()
     load().apss_default_opts(ctypes.byref(o))
     o.stream = stream
     o.query_safe = 1 if query_safe else 0
     o.head_dims = head_dims
+    o.variant = variant
     return o
 
 
@@ -268,7 +269,7 @@ class Index:
 
     @classmethod
     def build(cls, V, t_build: float, stream=None, query_safe: bool = True, head_dims: int = 0,
-              on_device: bool = False) -> "Index":
+              on_device: bool = False, variant: int = -1) -> "Index":
         """V: object with n, m, row_ptr, col, val (numpy), or a tuple (n, m, row_ptr, col, val) of tensors."""
         if isinstance(V, tuple):
             n, m, rp, col, val = V
@@ -281,7 +282,7 @@ class Index:
             val = torch.from_numpy(np.ascontiguousarray(val, np.float32)).cuda()
         if stream is None:
             stream = current_stream_handle()
-        h = build_index(n, m, rp, col, val, t_build, default_opts(stream, query_safe, head_dims))
+        h = build_index(n, m, rp, col, val, t_build, default_opts(stream, query_safe, head_dims, variant))
         return cls(h, int(n), int(m))
 
     def join(self, t: float):

@@ -117,17 +117,20 @@ struct apss_index {
   apss_opts opts;
   int64_t n = 0, m = 0, nnz = 0, P = 0;
   float t_build = 0.0f;
-  int32_t H = 0, CB = 0;
-  int64_t nb = 0;
+  int32_t H = 0;
   RankRows rows;          // corpus rows in rank space (densest dimension first)
   DBuf<RowStat> rs;
   DBuf<int32_t> rank, inv;
   DBuf<float> mw_r;       // maxweight by rank
   DBuf<int64_t> off;
   DBuf<Post> post;
-  DBuf<uint32_t> hoff;
+  DBuf<uint32_t> post4;   // packed copy of post for streaming
+  // per-block list offsets for each block width in use (index 0: 1024 rows, 1: 2048 rows)
+  DBuf<uint32_t> hoff[2];
+  int64_t hoff_nb[2] = {0, 0};
+  int variant = 0;
   // join workspace
-  DBuf<uint2> cur;
+  DBuf<uint32_t> cur_pos, cur_ny;
   DBuf<uint64_t> raw_key;
   DBuf<float> raw_sim;
   DBuf<unsigned long long> counters;
@@ -214,6 +217,24 @@ int stage_csr(apss_index* ix, int64_t n, const int64_t* row_ptr, const int32_t* 
     return APSS_EINVAL;
   }
   *nnz_out = nnz;
+  return APSS_OK;
+}
+
+int hoff_slot(int cb) { return cb == 1024 ? 0 : 1; }
+
+// Per-(block, rank) list offsets for the block width of a tile variant.
+int ensure_hoff(apss_index* ix, int variant) {
+  int qt = 0, cb = 0;
+  if (join_variant_geometry(variant, &qt, &cb)) {
+    set_error("unknown join variant %d", variant);
+    return APSS_EINVAL;
+  }
+  const int slot = hoff_slot(cb);
+  if (ix->hoff[slot].p) return APSS_OK;
+  const int64_t nb = (ix->n + cb - 1) / cb;
+  CHK(ix->hoff[slot].alloc((nb + 1) * (int64_t)ix->H), "alloc block offsets");
+  CHK(launch_block_offsets(ix->off.p, ix->post.p, ix->H, nb, cb, ix->hoff[slot].p, ix->stream), "block offsets");
+  ix->hoff_nb[slot] = nb;
   return APSS_OK;
 }
 
@@ -307,17 +328,18 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   DBuf<int64_t> scan2;
   CHK(scan2.alloc(scan_tmp_elems(m + 1)), "alloc");
   CHK(exclusive_scan_i64(ix->off.p, m + 1, scan2.p, nullptr, s), "scan");
-  CHK(ix->post.alloc(P), "alloc");
+  // one padding entry after the last list lets the join read position p + 1 for any p < P
+  CHK(ix->post.alloc(P + 1), "alloc");
+  CHK(fill_u64((uint64_t*)ix->post.p + P, ~0ull, 1, s), "fill");
   CHK(launch_unpack_post(ss.v64a.p, P, ix->post.p, s), "post");
+  CHK(ix->post4.alloc(P + 1), "alloc");
+  CHK(launch_pack_post4(ix->post.p, P, ix->post4.p, s), "post4");
 
-  // per-block offsets of the dense lists
-  ix->CB = join_block_rows();
-  ix->nb = (n + ix->CB - 1) / ix->CB;
-  int32_t H = ix->opts.head_dims > 0 ? ix->opts.head_dims : 4096;
+  // per-block offsets of the dense lists, for the default tile variant
+  int32_t H = ix->opts.head_dims > 0 ? ix->opts.head_dims : 32768;
   if (H > m) H = (int32_t)m;
   ix->H = H;
-  CHK(ix->hoff.alloc((ix->nb + 1) * (int64_t)H), "alloc");
-  CHK(launch_block_offsets(ix->off.p, ix->post.p, H, ix->nb, ix->CB, ix->hoff.p, s), "block offsets");
+  if ((rc = ensure_hoff(ix, ix->variant))) return rc;
   CHK(hipStreamSynchronize(s), "build_index");
   // sort scratch is re-grown on demand by the joins
   ss.k1.release();
@@ -345,7 +367,16 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     if (!ix->ev[e]) CHK(hipEventCreate(&ix->ev[e]), "event");
   CHK(hipEventRecord(ix->ev[0], s), "event");
   if (Q.n == 0 || ix->n == 0) return APSS_OK;
-  CHK(ix->cur.reserve(Q.nnz), "alloc cursors");
+  const int variant = ix->variant;
+  int QT = 0, CB = 0;
+  if (join_variant_geometry(variant, &QT, &CB)) {
+    set_error("unknown join variant %d", variant);
+    return APSS_EINVAL;
+  }
+  int rc0 = ensure_hoff(ix, variant);
+  if (rc0) return rc0;
+  CHK(ix->cur_pos.reserve(Q.nnz), "alloc cursors");
+  CHK(ix->cur_ny.reserve(Q.nnz), "alloc cursors");
   CHK(ix->counters.reserve(C_NUM), "alloc counters");
   if (!ix->raw_key.p) {
     const int64_t cap0 = std::max<int64_t>(1 << 20, 16 * std::max(ix->n, Q.n));
@@ -354,10 +385,8 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
   }
   const int bj = ceil_log2((uint64_t)(triangle ? ix->n : ix->n));
   const int bi = ceil_log2((uint64_t)(triangle ? ix->n : Q.n));
-  const int QT = join_tile_queries();
   for (int attempt = 0; attempt < 2; ++attempt) {
     CHK(hipEventRecord(ix->ev[0], s), "event");
-    CHK(launch_init_cursors(Q.rc, Q.nnz, ix->off.p, ix->post.p, ix->H, ix->cur.p, s), "cursors");
     CHK(fill_u64((uint64_t*)ix->counters.p, 0ull, C_NUM, s), "fill");
     JoinArgs a;
     a.rp = ix->rows.rp.p;
@@ -365,9 +394,10 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     a.rs = ix->rs.p;
     a.off = ix->off.p;
     a.post = ix->post.p;
-    a.hoff = ix->hoff.p;
+    a.post4 = ix->post4.p;
+    a.hoff = ix->hoff[hoff_slot(CB)].p;
     a.H = ix->H;
-    a.nb = ix->nb;
+    a.nb = ix->hoff_nb[hoff_slot(CB)];
     a.n = ix->n;
     a.qrp = Q.rp;
     a.qrc = Q.rc;
@@ -376,7 +406,8 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     a.t = t;
     a.nq = Q.n;
     a.triangle = triangle;
-    a.cur = ix->cur.p;
+    a.cur_pos = ix->cur_pos.p;
+    a.cur_ny = ix->cur_ny.p;
     a.ntiles = (Q.n + QT - 1) / QT;
     a.out_key = ix->raw_key.p;
     a.out_sim = ix->raw_sim.p;
@@ -384,7 +415,7 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     a.bj = bj;
     a.counters = ix->counters.p;
     CHK(hipEventRecord(ix->ev[1], s), "event");
-    CHK(launch_join(a, s), "join kernel");
+    CHK(launch_join(a, variant, s), "join kernel");
     CHK(hipEventRecord(ix->ev[2], s), "event");
     unsigned long long c[C_NUM];
     CHK(hipMemcpyAsync(c, ix->counters.p, sizeof(c), hipMemcpyDeviceToHost, s), "read counters");
@@ -552,7 +583,7 @@ void apss_default_opts(apss_opts* o) {
   o->struct_size = (int32_t)sizeof(apss_opts);
   o->stream = nullptr;
   o->query_safe = 1;
-  o->block_rows = 0;
+  o->variant = -1;
   o->head_dims = 0;
 }
 
@@ -580,8 +611,8 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
     }
     o = *opts;
   }
-  if (o.block_rows != 0 && o.block_rows != join_block_rows()) {
-    set_error("block_rows %d not available (compiled block: %d)", o.block_rows, join_block_rows());
+  if (o.variant < -1 || o.variant >= join_num_variants()) {
+    set_error("variant %d outside [-1, %d)", o.variant, join_num_variants());
     return APSS_EINVAL;
   }
   apss_index* ix = new (std::nothrow) apss_index();
@@ -594,6 +625,11 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
   ix->n = n;
   ix->m = m;
   ix->t_build = t_build;
+  ix->variant = o.variant >= 0 ? o.variant : 0;
+  if (const char* ev = getenv("APSS_VARIANT")) {
+    const int v = atoi(ev);
+    if (v >= 0 && v < join_num_variants()) ix->variant = v;
+  }
   (void)hipGetDevice(&ix->device);
   int rc = build_impl(ix, row_ptr, col, val, on_device);
   if (rc) {

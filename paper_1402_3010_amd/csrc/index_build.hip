@@ -8,6 +8,8 @@
 //                                     the leading components with b < t are x'
 //  k_count_indexed / k_emit_indexed   inverted lists of the indexed parts, by vector id
 //  k_block_offsets                    where each dense list enters each corpus block
+#include <hip/hip_fp16.h>
+
 #include "apss_internal.h"
 #include "index_build.h"
 
@@ -178,6 +180,18 @@ __global__ void k_unpack_post(const uint64_t* __restrict__ vals, int64_t P, Post
   }
 }
 
+// Packed copy of the list entries for streaming: low 16 bits = vector id mod
+// 2^16, high 16 bits = the weight as an IEEE half rounded toward +inf (the
+// next half up when round-to-nearest fell below the weight).
+__global__ void k_pack_post4(const Post* __restrict__ post, int64_t P, uint32_t* __restrict__ post4) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
+    const Post p = post[k];
+    unsigned short h = __half_as_ushort(__float2half_rn(p.w));
+    if (__half2float(__ushort_as_half(h)) < p.w) ++h;
+    post4[k] = (p.y & 0xFFFFu) | ((uint32_t)h << 16);
+  }
+}
+
 // hoff[b * H + r] = first position in list r whose vector id is >= b * CB.
 __global__ void k_block_offsets(const int64_t* __restrict__ off, const Post* __restrict__ post, int32_t H, int64_t nb,
                                 int32_t CB, uint32_t* __restrict__ hoff) {
@@ -306,6 +320,11 @@ hipError_t launch_count_ranks(const uint64_t* keys, int64_t P, int64_t* cnt, hip
 
 hipError_t launch_unpack_post(const uint64_t* vals, int64_t P, Post* post, hipStream_t s) {
   LAUNCH(k_unpack_post, P, vals, P, post);
+  return hipSuccess;
+}
+
+hipError_t launch_pack_post4(const Post* post, int64_t P, uint32_t* post4, hipStream_t s) {
+  LAUNCH(k_pack_post4, P, post, P, post4);
   return hipSuccess;
 }
 

@@ -12,6 +12,7 @@ struct JoinArgs {
   const RowStat* rs;      // [n]
   const int64_t* off;     // [m+1] list offsets by rank
   const Post* post;       // [P]   list entries, vector ids ascending within a list
+  const uint32_t* post4;  // [P]   the same entries packed: id mod 2^16 | half weight (rounded up) << 16
   const uint32_t* hoff;   // [(nb+1) * H] first entry of list r at or after block b
   int32_t H;              // ranks with block offsets
   int64_t nb;             // corpus blocks
@@ -24,7 +25,8 @@ struct JoinArgs {
   float t;                // threshold when qt is NULL
   int64_t nq;
   int32_t triangle;       // 1: self-join, query q only meets corpus rows y < q
-  uint2* cur;             // [qnnz] sparse-list cursors {position, next vector id}
+  uint32_t* cur_pos;      // [qnnz] list cursors of tiles too large to stage in LDS
+  uint32_t* cur_ny;       // [qnnz] vector id at each such cursor
   int64_t ntiles;
   // output
   uint64_t* out_key;      // [cap] (i << bj) | j
@@ -34,11 +36,10 @@ struct JoinArgs {
   unsigned long long* counters;  // [C_NUM]
 };
 
-int join_tile_queries();
-int join_block_rows();
-hipError_t launch_join(const JoinArgs& a, hipStream_t s);
-hipError_t launch_init_cursors(const RComp* qrc, int64_t qnnz, const int64_t* off, const Post* post, int32_t H,
-                               uint2* cur, hipStream_t s);
+// Compiled tile variants of the join kernel.
+int join_num_variants();
+int join_variant_geometry(int variant, int* queries_per_tile, int* block_rows);
+hipError_t launch_join(const JoinArgs& a, int variant, hipStream_t s);
 hipError_t launch_unpack_pairs(const uint64_t* keys, const float* sim, int64_t cnt, int bj, uint32_t* oi,
                                uint32_t* oj, float* os, hipStream_t s);
 

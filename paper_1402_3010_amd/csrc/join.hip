@@ -27,6 +27,8 @@
 //     lane-strided order and a fixed butterfly, so the result depends only on
 //     (q, y); if it lies within kBand of t the pair is decided by a double
 //     rescore.  Emitted pairs are compacted per wave (ballot + prefix).
+#include <hip/hip_fp16.h>
+
 #include "apss_internal.h"
 #include "join.h"
 
@@ -34,7 +36,28 @@ namespace apss {
 
 namespace {
 
-__device__ __forceinline__ uint32_t fixp(float a, float b) { return __float2uint_ru(__fmul_rn(a, b) * kFix); }
+// q_d * y_d in 2^-30 units, rounded up (the product is at most 1, so the
+// scaled value is exact in float and below 2^30 + 1)
+__device__ __forceinline__ uint32_t fixp(float a, float b) { return (uint32_t)ceilf(__fmul_rn(a, b) * kFix); }
+
+// Weight of a packed list entry: bits 16..31 hold the weight as an IEEE
+// half rounded up, so accumulated scores only over-estimate (bits 0..15 hold
+// the vector id modulo 2^16, its offset inside any power-of-two block).
+__device__ __forceinline__ float w16(uint32_t e) {
+  return __half2float(__ushort_as_half((unsigned short)(e >> 16)));
+}
+
+// segments at least this long are streamed by a whole wave
+constexpr int kLongSeg = 32;
+
+// Values known to be equal across the wave, moved to scalar registers so that
+// loops and branches on them stay scalar.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   s = __fadd_rn(a, b);
@@ -42,35 +65,63 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = __fadd_rn(__fsub_rn(a, __fsub_rn(s, z)), __fsub_rn(b, z));
 }
 
-template <int QT, int CB, int NT, int RD, int SQ, int QB>
+// One dense-list segment of a (tile, block): list positions [pos, pos + len)
+// feed query slot qi with weight w.  lenq = len | qi << 16.
+struct Seg {
+  uint32_t pos;
+  uint32_t lenq;
+  float w;
+};
+
+template <int QT_, int CB_, int NT_, int RD_, int SQ_, int QB_, int U_, int UL_, int WPE_>
+struct Cfg {
+  static constexpr int QT = QT_;  // queries per tile
+  static constexpr int CB = CB_;  // corpus rows per block (accumulator width)
+  static constexpr int NT = NT_;  // threads per workgroup
+  static constexpr int RD = RD_;  // ranks with a dense per-query lookup table
+  static constexpr int SQ = SQ_;  // survivor queue capacity
+  static constexpr int QB = QB_;  // tile components staged in LDS
+  static constexpr int U = U_;    // list loads in flight per lane, short segments
+  static constexpr int UL = UL_;  // list loads in flight per lane, long segments
+  static constexpr int WPE = WPE_;  // waves per SIMD the register budget must allow
+};
+
+template <class C>
 struct Smem {
-  uint32_t acc[QT * CB];
-  float qd[QT * RD];
-  int4 seg[NT];  // x = first list position, y = length, z = query weight bits, w = query slot
-  int32_t segpre[NT + 1];
-  uint2 sq[SQ];  // x = slot * CB + local y, y = fixed-point score (0 = dropped)
-  RComp qrow[QB];
-  int64_t qoff[QT + 1];
-  float qmw[QT];
-  float qt[QT];
-  int32_t qlen[QT];
-  int32_t qhead[QT];
-  int32_t wsum[NT / 64];
-  int32_t nseg;
+  uint32_t acc[C::QT * C::CB];
+  float qd[C::QT * C::RD];
+  Seg seg[C::QB];
+  int32_t segpre[C::QB + 1];
+  uint4 sq[C::SQ];  // x = slot << 16 | local y, y = fixed-point score (0 = dropped), z = row start, w = cut | len << 16
+  RComp qrow[C::QB];     // staged components of the tile
+  uint2 cur[C::QB];      // list cursor of each staged component: {position, vector id at it}
+  uint8_t cqi[C::QB];    // query slot of each staged component
+  int64_t qoff[C::QT + 1];
+  float qmw[C::QT];
+  float qt[C::QT];
+  int32_t qlen[C::QT];
+  int32_t qhead[C::QT];
+  int32_t wsum[C::NT / 64];
+  int32_t nseg;    // long segments, stored from the front of seg[]
+  int32_t nshort;  // short segments, stored from the back of seg[]
+  int32_t lnext;   // next long segment to hand out
   int32_t qcount;
   int32_t ovf;
-  int32_t staged;
   unsigned long long cnt[C_NUM];
 };
 
-template <int QT, int CB, int NT, int RD, int SQ, int QB>
-__global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
+template <class C>
+__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE))) void k_join(JoinArgs a) {
+  constexpr int QT = C::QT, CB = C::CB, NT = C::NT, RD = C::RD, SQ = C::SQ, QB = C::QB, U = C::U, UL = C::UL;
   constexpr int NW = NT / 64;
-  using S = Smem<QT, CB, NT, RD, SQ, QB>;
-  __shared__ S sm;
+  constexpr int KMAX = QB / NT;  // staged components per thread
+  constexpr int YPT = CB / NT;   // corpus rows per thread in the filter
+  static_assert(KMAX >= 1 && QB % NT == 0 && CB % NT == 0, "tile geometry");
+  static_assert(CB <= 65536 && QT <= 256, "survivor packing");
+  __shared__ Smem<C> sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = uni(tid >> 6);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   const int64_t tile = a.ntiles - 1 - (int64_t)blockIdx.x;  // heaviest tiles first
@@ -85,14 +136,16 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
   if (tid < C_NUM) sm.cnt[tid] = 0;
   if (tid == 0) {
     sm.nseg = 0;
+    sm.nshort = 0;
+    sm.lnext = 0;
     sm.qcount = 0;
     sm.ovf = 0;
   }
   for (int e = tid; e < QT * RD; e += NT) sm.qd[e] = 0.0f;
   for (int e = tid; e < QT * CB; e += NT) sm.acc[e] = 0u;
   __syncthreads();
-  const int64_t qbase = sm.qoff[0];
-  const int64_t tile_nnz = sm.qoff[qn] - qbase;
+  const int64_t qbase = uni64(sm.qoff[0]);
+  const int64_t tile_nnz = uni64(sm.qoff[qn]) - qbase;
   const bool staged = tile_nnz <= QB;
   if (tid < qn) {
     const int64_t r0 = sm.qoff[tid], r1 = sm.qoff[tid + 1];
@@ -110,10 +163,34 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
     while (qi + 1 < qn && sm.qoff[qi + 1] <= k) ++qi;
     return qi;
   };
+  int64_t last_b = -1;
+  if (qn > 0 && a.n > 0) last_b = a.triangle ? (q0 + qn - 1) / CB : (a.nb - 1);
+
+  // stage the tile, fill the dense lookup table, place every list cursor at
+  // its list start, and fetch block 0's segment ends of the dense lists
+  uint32_t hn[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) hn[j] = 0;
   for (int64_t k = tid; k < tile_nnz; k += NT) {
     const RComp c = a.qrc[qbase + k];
-    if (staged) sm.qrow[k] = c;
-    if (c.r < RD) sm.qd[find_slot(qbase + k) * RD + c.r] = c.w;
+    const int qi = find_slot(qbase + k);
+    if (c.r < RD) sm.qd[qi * RD + c.r] = c.w;
+    const int64_t p0 = a.off[c.r];
+    uint32_t ny = 0;
+    if (c.r >= a.H) ny = p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
+    if (staged) {
+      sm.qrow[k] = c;
+      sm.cqi[k] = (uint8_t)qi;
+      sm.cur[k] = make_uint2((uint32_t)p0, ny);
+      if (c.r < a.H && last_b >= 0) {
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+          if (k == (int64_t)j * NT + tid) hn[j] = a.hoff[(int64_t)a.H + c.r];
+      }
+    } else {
+      a.cur_pos[qbase + k] = (uint32_t)p0;
+      a.cur_ny[qbase + k] = ny;
+    }
   }
   __syncthreads();
 
@@ -132,57 +209,145 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
 
   unsigned long long c_visit = 0, c_tail = 0, c_cand = 0, c_surv = 0, c_ver = 0, c_band = 0;
 
-  int64_t last_b = -1;
-  if (qn > 0 && a.n > 0) last_b = a.triangle ? (q0 + qn - 1) / CB : (a.nb - 1);
-
   for (int64_t b = 0; b <= last_b; ++b) {
     const int64_t blk0 = b * CB;
     const int64_t blk1 = (blk0 + CB) < a.n ? (blk0 + CB) : a.n;
-    const uint32_t* hb = a.hoff + b * (int64_t)a.H;
+    const uint32_t* hend = a.hoff + (b + 1) * (int64_t)a.H;   // end of each dense list's block segment
+    const uint32_t* hnext = a.hoff + (b + 2) * (int64_t)a.H;  // same for the next block (b < last_b)
+
+    // per-row data of the filter's first rows; the loads overlap the accumulation
+    RowStat stN;
+    uint32_t ysN, ylN;
+    auto load_rows = [&](int yi) {
+      const int64_t y = blk0 + yi * NT + tid;
+      const int64_t yc = y < blk1 ? y : blk0;
+      stN = a.rs[yc];
+      const uint32_t r0 = (uint32_t)a.rp[yc];  // row offsets fit 32 bits (nnz < 2^32)
+      ysN = r0;
+      ylN = (uint32_t)a.rp[yc + 1] - r0;
+    };
+    load_rows(0);
 
     // ------------------------------------------------------------ accumulate
-    for (int64_t cb = 0; cb < tile_nnz; cb += NT) {
-      const int64_t k = cb + tid;
-      bool has_seg = false;
-      int4 sg = make_int4(0, 0, 0, 0);
-      if (k < tile_nnz) {
-        const int64_t kk = qbase + k;
-        const RComp c = staged ? sm.qrow[k] : a.qrc[kk];
-        const int qi = find_slot(kk);
-        if (c.r < a.H) {
-          const uint32_t s0 = hb[c.r], s1 = hb[a.H + c.r];
-          if (s1 > s0) {
-            has_seg = true;
-            sg = make_int4((int)s0, (int)(s1 - s0), __float_as_int(c.w), qi);
+    for (int64_t cb = 0; cb < tile_nnz; cb += QB) {
+      // pass 1: every component's segment of a dense list is known from the
+      // block offsets; sparse lists with an entry in this block get their
+      // first two entries loaded (no waiting here)
+      bool thit[KMAX];
+      Post t0[KMAX], t1[KMAX];
+      uint32_t tpos[KMAX], tend[KMAX];
+      float tw[KMAX];
+      int tqi[KMAX];
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        const int64_t k = cb + (int64_t)j * NT + tid;
+        bool has_seg = false;
+        Seg sg = {0u, 0u, 0.0f};
+        thit[j] = false;
+        tpos[j] = 0;
+        tend[j] = 0;
+        tw[j] = 0.0f;
+        tqi[j] = 0;
+        if (k < tile_nnz) {
+          RComp c;
+          int qi;
+          uint32_t pos, ny;
+          if (staged) {
+            c = sm.qrow[k];
+            qi = sm.cqi[k];
+            const uint2 cu = sm.cur[k];
+            pos = cu.x;
+            ny = cu.y;
+          } else {
+            c = a.qrc[qbase + k];
+            qi = find_slot(qbase + k);
+            pos = a.cur_pos[qbase + k];
+            ny = a.cur_ny[qbase + k];
           }
-        } else {
-          uint2 cu = a.cur[kk];
-          if ((int64_t)cu.y < blk1) {
-            uint32_t pos = cu.x;
-            const uint32_t end = (uint32_t)a.off[c.r + 1];
-            uint32_t ny = cu.y;
-            do {
-              const float pw = a.post[pos].w;
-              atomicAdd(&sm.acc[qi * CB + (int)(ny - (uint32_t)blk0)], fixp(c.w, pw));
-              ++c_tail;
-              ++pos;
-              ny = pos < end ? a.post[pos].y : 0xFFFFFFFFu;
-            } while ((int64_t)ny < blk1);
-            a.cur[kk] = make_uint2(pos, ny);
+          if (c.r < a.H) {
+            uint32_t e;
+            if (staged) {
+              e = hn[j];
+              if (b < last_b) hn[j] = hnext[c.r];  // prefetch for the next block
+            } else {
+              e = hend[c.r];
+            }
+            if (e > pos) {
+              has_seg = true;
+              sg.pos = pos;
+              sg.lenq = (e - pos) | ((uint32_t)qi << 16);
+              sg.w = c.w;
+              if (staged) sm.cur[k] = make_uint2(e, 0u);
+              else a.cur_pos[qbase + k] = e;
+            }
+          } else if ((int64_t)ny < blk1) {
+            thit[j] = true;
+            tpos[j] = pos;
+            tw[j] = c.w;
+            tqi[j] = qi;
+            tend[j] = (uint32_t)a.off[c.r + 1];
+            t0[j] = a.post[pos];
+            t1[j] = a.post[pos + 1];  // the list array carries one padding entry
+          }
+        }
+        // long segments go to the front (one wave each), short ones to the
+        // back (split evenly over all lanes)
+        const bool is_long = has_seg && (sg.lenq & 0xFFFFu) >= (uint32_t)kLongSeg;
+        const bool is_short = has_seg && !is_long;
+        const uint64_t ml = __ballot(is_long);
+        const uint64_t msh = __ballot(is_short);
+        int lb = 0, sb = 0;
+        if (lane == 0) {
+          if (ml) lb = atomicAdd(&sm.nseg, (int)__popcll(ml));
+          if (msh) sb = atomicAdd(&sm.nshort, (int)__popcll(msh));
+        }
+        lb = __shfl(lb, 0);
+        sb = __shfl(sb, 0);
+        if (is_long) sm.seg[lb + (int)__popcll(ml & lt)] = sg;
+        if (is_short) sm.seg[QB - 1 - (sb + (int)__popcll(msh & lt))] = sg;
+      }
+      // pass 2: sparse lists, usually one entry per block
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        if (thit[j]) {
+          const int64_t k = cb + (int64_t)j * NT + tid;
+          uint32_t pos = tpos[j];
+          const uint32_t end = tend[j];
+          const int ab = tqi[j] * CB - (int)blk0;
+          atomicAdd(&sm.acc[ab + (int)t0[j].y], fixp(tw[j], t0[j].w));
+          ++c_tail;
+          ++pos;
+          uint32_t ny = pos < end ? t1[j].y : 0xFFFFFFFFu;
+          while ((int64_t)ny < blk1) {
+            const Post p = a.post[pos];
+            atomicAdd(&sm.acc[ab + (int)p.y], fixp(tw[j], p.w));
+            ++c_tail;
+            ++pos;
+            ny = pos < end ? a.post[pos].y : 0xFFFFFFFFu;
+          }
+          if (staged) {
+            sm.cur[k] = make_uint2(pos, ny);
+          } else {
+            a.cur_pos[qbase + k] = pos;
+            a.cur_ny[qbase + k] = ny;
           }
         }
       }
-      const uint64_t m = __ballot(has_seg);
-      int sbase = 0;
-      if (lane == 0 && m) sbase = atomicAdd(&sm.nseg, (int)__popcll(m));
-      sbase = __shfl(sbase, 0);
-      if (has_seg) sm.seg[sbase + (int)__popcll(m & lt)] = sg;
       __syncthreads();
-      const int ns = sm.nseg;
-      // exclusive scan of segment lengths
+      const int nl = uni(sm.nseg);
+      const int ns = uni(sm.nshort);
+      Seg* const sseg = sm.seg + (QB - ns);  // the short segments, contiguous
+      // exclusive scan of the short segments' lengths (KMAX consecutive entries per thread)
       {
-        const int len = tid < ns ? sm.seg[tid].y : 0;
-        int incl = len;
+        int loc[KMAX];
+        int run = 0;
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+          const int e = tid * KMAX + j;
+          loc[j] = run;
+          run += e < ns ? (int)(sseg[e].lenq & 0xFFFFu) : 0;
+        }
+        int incl = run;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
           const int u = __shfl_up(incl, o, 64);
@@ -192,13 +357,23 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
         __syncthreads();
         int woff = 0;
         for (int w = 0; w < wave; ++w) woff += sm.wsum[w];
-        if (tid < ns) sm.segpre[tid] = woff + incl - len;
+        const int excl = woff + incl - run;
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+          const int e = tid * KMAX + j;
+          if (e < ns) sm.segpre[e] = excl + loc[j];
+        }
         if (tid == NT - 1) sm.segpre[ns] = woff + incl;
       }
       __syncthreads();
-      if (tid == 0) sm.nseg = 0;
-      const int L = sm.segpre[ns];
-      if (tid == 0) c_visit += (unsigned long long)L;
+      const int L = uni(sm.segpre[ns]);
+      if (tid == 0) {
+        c_visit += (unsigned long long)L;
+        sm.nseg = 0;
+        sm.nshort = 0;
+      }
+      // short segments: each wave takes a contiguous range of their visits;
+      // every lane keeps U list loads in flight
       {
         const int per = (((L + NW - 1) / NW) + 63) & ~63;
         const int vbeg = wave * per;
@@ -211,18 +386,88 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
             else hi = mid - 1;
           }
           int s = lo, cs = -1, pre = 0;
-          int4 S = make_int4(0, 0, 0, 0);
-          for (int base = vbeg; base < vend; base += 64) {
-            const int v = base + lane;
-            if (v < vend) {
+          Seg S = {0u, 0u, 0.0f};
+          for (int base = vbeg; base < vend; base += 64 * U) {
+            // resolve every visit's segment first (LDS only), then issue all
+            // list loads back to back with clamped addresses, then accumulate
+            uint32_t pos[U], qwb[U];
+            int qs[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int vr = base + u * 64 + lane;
+              const int v = vr < vend ? vr : vend - 1;
               while (sm.segpre[s + 1] <= v) ++s;
               if (s != cs) {
-                S = sm.seg[s];
+                S = sseg[s];
                 pre = sm.segpre[s];
                 cs = s;
               }
-              const Post p = a.post[(uint32_t)S.x + (uint32_t)(v - pre)];
-              atomicAdd(&sm.acc[S.w * CB + (int)(p.y - (uint32_t)blk0)], fixp(__int_as_float(S.z), p.w));
+              pos[u] = S.pos + (uint32_t)(v - pre);
+              qwb[u] = __float_as_uint(S.w);
+              qs[u] = vr < vend ? (int)(S.lenq >> 16) : -1;
+            }
+            uint32_t p[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) p[u] = a.post4[pos[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+              if (qs[u] >= 0)
+                atomicAdd(&sm.acc[qs[u] * CB + (int)(p[u] & (CB - 1))], fixp(__uint_as_float(qwb[u]), w16(p[u])));
+          }
+        }
+      }
+      // long segments: wave w walks segments w, w + NW, ... in chunks of 64
+      // entries (one entry per lane) with all bookkeeping uniform; U chunks,
+      // possibly from different segments, are loaded before accumulating
+      {
+        int si = wave, off = 0;
+        uint32_t spos = 0, slenq = 0;
+        float sw = 0.0f;
+        int cur_si = -1;
+        while (si < nl) {
+          uint32_t cpos[UL];
+          int ccnt[UL], cab[UL];
+          float cw[UL];
+#pragma unroll
+          for (int u = 0; u < UL; ++u) {
+            ccnt[u] = 0;
+            cpos[u] = 0;
+            cab[u] = 0;
+            cw[u] = 0.0f;
+            if (si < nl) {
+              if (si != cur_si) {
+                const Seg S = sm.seg[si];
+                spos = __builtin_amdgcn_readfirstlane(S.pos);
+                slenq = __builtin_amdgcn_readfirstlane(S.lenq);
+                sw = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(S.w))) * kFix;
+                cur_si = si;
+              }
+              const int len = (int)(slenq & 0xFFFFu);
+              const int left = len - off;
+              ccnt[u] = left < 64 ? left : 64;
+              cpos[u] = spos + (uint32_t)off;
+              cab[u] = (int)(slenq >> 16) * CB;
+              cw[u] = sw;
+              off += 64;
+              if (off >= len) {
+                off = 0;
+                si += NW;
+              }
+            }
+          }
+          // unconditional loads (an empty slot re-reads a valid entry) keep the
+          // U loads back to back
+          uint32_t p[UL];
+#pragma unroll
+          for (int u = 0; u < UL; ++u) {
+            const int li = lane < ccnt[u] ? lane : (ccnt[u] > 0 ? ccnt[u] - 1 : 0);
+            p[u] = a.post4[(ccnt[u] > 0 ? cpos[u] : cpos[0]) + (uint32_t)li];
+          }
+#pragma unroll
+          for (int u = 0; u < UL; ++u) {
+            if (ccnt[u] > 0) {
+              if (lane == 0) c_visit += (unsigned long long)ccnt[u];
+              if (lane < ccnt[u]) atomicAdd(&sm.acc[cab[u] + (int)(p[u] & (CB - 1))], (uint32_t)ceilf(cw[u] * w16(p[u])));
             }
           }
         }
@@ -232,20 +477,24 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
 
     // ------------------------------------------------------------ filter, verify, rescore
     auto drain = [&]() {
-      const int ns = sm.qcount < SQ ? sm.qcount : SQ;
-      // verify: one lane per survivor, s = A + dot(q, y')
+      const int ns = uni(sm.qcount < SQ ? sm.qcount : SQ);
+      // verify: one lane per survivor, s = A + dot(q, y'); y' is the first
+      // cut components of the row, densest dimension first
       for (int e = tid; e < ns; e += NT) {
-        const uint2 it = sm.sq[e];
-        const int qi = (int)(it.x / CB);
-        const int64_t y = blk0 + (int64_t)(it.x % CB);
-        const int64_t ys = a.rp[y];
-        const int cut = a.rs[y].cut;
-        float s = (float)it.y * kInvFix;
-        for (int k = 0; k < cut; ++k) {
-          const RComp c = a.rc[ys + k];
-          s += qlookup(qi, c.r) * c.w;
+        const uint4 it = sm.sq[e];
+        const int qi = (int)(it.x >> 16);
+        uint32_t cut = it.w & 0xFFFFu;
+        if ((it.w >> 16) == 0xFFFFu) cut = (uint32_t)a.rs[blk0 + (it.x & 0xFFFFu)].cut;
+        float sc = (float)it.y * kInvFix;
+        for (uint32_t k0 = 0; k0 < cut; k0 += 4) {
+          RComp c[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) c[u] = a.rc[it.z + (k0 + u < cut ? k0 + u : cut - 1)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (k0 + u < cut) sc += qlookup(qi, c[u].r) * c[u].w;
         }
-        if (s >= sm.qt[qi] - kSlack) ++c_ver;
+        if (sc >= sm.qt[qi] - kSlack) ++c_ver;
         else sm.sq[e].y = 0u;
       }
       __syncthreads();
@@ -256,11 +505,12 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
         while (fm) {
           const int l = __ffsll((unsigned long long)fm) - 1;
           fm &= fm - 1;
-          const uint2 it = sm.sq[base + l];
-          const int qi = (int)(it.x / CB);
-          const int64_t y = blk0 + (int64_t)(it.x % CB);
-          const int64_t ys = a.rp[y];
-          const int ylen = (int)(a.rp[y + 1] - ys);
+          const uint4 it = sm.sq[base + l];
+          const int qi = (int)(it.x >> 16);
+          const int64_t y = blk0 + (int64_t)(it.x & 0xFFFFu);
+          const int64_t ys = it.z;
+          int ylen = (int)(it.w >> 16);
+          if (ylen == 0xFFFF) ylen = (int)(a.rp[y + 1] - a.rp[y]);
           float hi = 0.0f, lo = 0.0f;
           for (int k = lane; k < ylen; k += 64) {
             const RComp c = a.rc[ys + k];
@@ -319,37 +569,34 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
       __syncthreads();
     };
 
-    for (int yb = 0; yb < CB; yb += NT) {
-      const int yl = yb + tid;
-      const int64_t y = blk0 + yl;
-      const bool yv = y < blk1;
-      RowStat st = {0, 0.0f, 0.0f, 0.0f};
-      int ylen = 0;
-      if (yv) {
-        st = a.rs[y];
-        ylen = (int)(a.rp[y + 1] - a.rp[y]);
-      }
-      for (;;) {
-        for (int qi = 0; qi < qn; ++qi) {
-          const int e = qi * CB + yl;
-          const uint32_t av = sm.acc[e];
-          bool want = false;
-          if (av) {
-            if (!yv || (a.triangle && y >= q0 + qi)) {
-              sm.acc[e] = 0u;
-            } else {
-              const float A = (float)av * kInvFix;
-              const float thr = sm.qt[qi] - kSlack;
-              const float qm = sm.qmw[qi];
-              const float mn = (float)(st.cut < sm.qlen[qi] ? st.cut : sm.qlen[qi]);
-              const bool ok = ((float)ylen * qm >= thr) && (A + mn * qm * st.pmw >= thr) && (A + st.pnrm >= thr);
-              if (ok) {
-                want = true;
-              } else {
-                sm.acc[e] = 0u;
-                ++c_cand;
-              }
-            }
+    for (bool first = true;; first = false) {
+      if (!first) load_rows(0);
+#pragma unroll 1
+      for (int yi = 0; yi < YPT; ++yi) {
+        const RowStat st = stN;
+        const uint32_t yst = ysN;
+        const int ylen = (int)ylN;
+        if (yi + 1 < YPT) load_rows(yi + 1);
+        const int yl = yi * NT + tid;
+        const int64_t y = blk0 + yl;
+        const bool yv = y < blk1;
+        const uint32_t packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) |
+                                ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
+        // slots beyond qn were never written and hold zeros
+        uint32_t av[QT];
+#pragma unroll
+        for (int qi = 0; qi < QT; ++qi) av[qi] = sm.acc[qi * CB + yl];
+#pragma unroll
+        for (int qi = 0; qi < QT; ++qi) {
+          bool want = false, retry = false;
+          if (av[qi] && yv && !(a.triangle && y >= q0 + qi)) {
+            const float A = (float)av[qi] * kInvFix;
+            const float thr = sm.qt[qi] - kSlack;
+            const float qm = sm.qmw[qi];
+            const int ql = sm.qlen[qi];
+            const float mn = (float)(st.cut < ql ? st.cut : ql);
+            want = ((float)ylen * qm >= thr) && (A + mn * qm * st.pmw >= thr) && (A + st.pnrm >= thr);
+            ++c_cand;
           }
           const uint64_t wm = __ballot(want);
           if (wm) {
@@ -359,23 +606,24 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
             if (want) {
               const int slot = qb + (int)__popcll(wm & lt);
               if (slot < SQ) {
-                sm.sq[slot] = make_uint2((uint32_t)(qi * CB + yl), av);
-                sm.acc[e] = 0u;
-                ++c_cand;
+                sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av[qi], yst, packed);
                 ++c_surv;
               } else {
+                retry = true;  // queue full: keep the entry for the next pass
+                --c_cand;
                 sm.ovf = 1;
               }
             }
           }
+          if (av[qi] && !retry) sm.acc[qi * CB + yl] = 0u;
         }
-        __syncthreads();
-        const int o = sm.ovf;
-        const int qc = sm.qcount;
-        __syncthreads();
-        if (o || qc >= SQ / 2 || (yb + NT >= CB && qc > 0)) drain();
-        if (!o) break;
       }
+      __syncthreads();
+      const int o = uni(sm.ovf);
+      const int qc = uni(sm.qcount);
+      __syncthreads();
+      if (qc > 0) drain();
+      if (!o) break;
     }
   }
 
@@ -388,17 +636,6 @@ __global__ __launch_bounds__(NT) void k_join(JoinArgs a) {
   atomicAdd(&sm.cnt[C_BAND], c_band);
   __syncthreads();
   if (tid < C_NUM && tid != C_MATCHES && sm.cnt[tid]) atomicAdd(&a.counters[tid], sm.cnt[tid]);
-}
-
-// Tail cursors: first entry of each sparse list a query component reads.
-__global__ void k_init_cursors(const RComp* __restrict__ qrc, int64_t qnnz, const int64_t* __restrict__ off,
-                               const Post* __restrict__ post, int32_t H, uint2* __restrict__ cur) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < qnnz; k += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = qrc[k].r;
-    if (r < H) continue;
-    const int64_t p0 = off[r], p1 = off[r + 1];
-    cur[k] = make_uint2((uint32_t)p0, p0 < p1 ? post[p0].y : 0xFFFFFFFFu);
-  }
 }
 
 __global__ void k_unpack_pairs(const uint64_t* __restrict__ keys, const float* __restrict__ sim, int64_t cnt, int bj,
@@ -421,13 +658,6 @@ unsigned grid(int64_t n, int threads = 256) {
 
 }  // namespace
 
-hipError_t launch_init_cursors(const RComp* qrc, int64_t qnnz, const int64_t* off, const Post* post, int32_t H,
-                               uint2* cur, hipStream_t s) {
-  if (qnnz <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init_cursors, dim3(grid(qnnz)), dim3(256), 0, s, qrc, qnnz, off, post, H, cur);
-  return hipGetLastError();
-}
-
 hipError_t launch_unpack_pairs(const uint64_t* keys, const float* sim, int64_t cnt, int bj, uint32_t* oi, uint32_t* oj,
                                float* os, hipStream_t s) {
   if (cnt <= 0) return hipSuccess;
@@ -435,22 +665,41 @@ hipError_t launch_unpack_pairs(const uint64_t* keys, const float* sim, int64_t c
   return hipGetLastError();
 }
 
-// Tile and block geometry of the compiled variant.
-constexpr int kQT = 8;
-constexpr int kCB = 2048;
-constexpr int kNT = 512;
-constexpr int kRD = 512;
-constexpr int kSQ = 2048;
-constexpr int kQB = 2048;
+// (queries per tile, corpus rows per block, threads, dense lookup ranks,
+//  survivor queue, staged components, loads in flight for short / long
+//  segments, waves per SIMD)
+using V0 = Cfg<8, 2048, 512, 512, 1024, 1024, 8, 8, 2>;
+using V1 = Cfg<8, 1024, 512, 128, 512, 1024, 4, 8, 4>;
+using V2 = Cfg<16, 1024, 512, 256, 1024, 1536, 8, 8, 2>;
+using V3 = Cfg<4, 2048, 256, 256, 512, 1024, 8, 8, 2>;
 
-int join_tile_queries() { return kQT; }
-int join_block_rows() { return kCB; }
+int join_num_variants() { return 4; }
 
-hipError_t launch_join(const JoinArgs& a, hipStream_t s) {
-  if (a.ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_join<kQT, kCB, kNT, kRD, kSQ, kQB>), dim3((unsigned)a.ntiles), dim3(kNT), 0, s,
-                     a);
+int join_variant_geometry(int v, int* qt, int* cb) {
+  switch (v) {
+    case 0: *qt = V0::QT; *cb = V0::CB; return 0;
+    case 1: *qt = V1::QT; *cb = V1::CB; return 0;
+    case 2: *qt = V2::QT; *cb = V2::CB; return 0;
+    case 3: *qt = V3::QT; *cb = V3::CB; return 0;
+    default: return -1;
+  }
+}
+
+template <class C>
+hipError_t launch_variant(const JoinArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_join<C>), dim3((unsigned)a.ntiles), dim3(C::NT), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_join(const JoinArgs& a, int variant, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  switch (variant) {
+    case 0: return launch_variant<V0>(a, s);
+    case 1: return launch_variant<V1>(a, s);
+    case 2: return launch_variant<V2>(a, s);
+    case 3: return launch_variant<V3>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace apss

@@ -268,3 +268,13 @@ def test_full_size_sampled(apss, name, t):
         d = exact_dot(V, i[k], j[k])
         assert d >= float(t) - 1e-5 and abs(d - s[k]) <= 1e-5
     assert st["matches"] == len(i)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_every_tile_variant(apss, variant):
+    V = make_corpus(spec_for("c2", n=9000))
+    t = np.float32(0.6)
+    i, j, s, st = gpu_join(apss, V, t, variant=variant)
+    assert_parity(i, j, s, oracle.join_plain(V, t), float(t), V)
+    pre = oracle.join_prefix(V, t, 4)
+    assert st["candidates"] == pre.candidates
