@@ -129,8 +129,15 @@ struct apss_index {
   DBuf<uint32_t> hoff[2];
   int64_t hoff_nb[2] = {0, 0};
   int variant = 0;
+  // range offsets of the sparse lists for one range width (rows)
+  DBuf<uint32_t> toff;
+  int64_t toff_rows = 0, toff_nR = 0;
   // join workspace
-  DBuf<uint32_t> cur_pos, cur_ny;
+  DBuf<uint32_t> wg_cur;
+  DBuf<int64_t> qcum;
+  DBuf<unsigned int> qctr;
+  DBuf<unsigned long long> scalar;
+  int grid[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   DBuf<uint64_t> raw_key;
   DBuf<float> raw_sim;
   DBuf<unsigned long long> counters;
@@ -312,6 +319,10 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   CHK(hipMemcpyAsync(&P, total.p, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read P");
   CHK(hipStreamSynchronize(s), "read P");
   ix->P = P;
+  if (4 * (P + 1) >= (1ll << 32)) {
+    set_error("index too large: %lld postings (the packed lists must stay below 4 GiB)", (long long)P);
+    return APSS_EINVAL;
+  }
 
   // inverted lists of the indexed parts: stable sort by rank keeps vector ids ascending
   CHK(ss.k1.reserve(P), "alloc");
@@ -375,9 +386,51 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
   }
   int rc0 = ensure_hoff(ix, variant);
   if (rc0) return rc0;
-  CHK(ix->cur_pos.reserve(Q.nnz), "alloc cursors");
-  CHK(ix->cur_ny.reserve(Q.nnz), "alloc cursors");
+  const int slot = hoff_slot(CB);
+  const int64_t nb = ix->hoff_nb[slot];
+  // work items: ranges of K blocks x query tiles
+  int K = std::max(1, 8192 / CB);
+  if (const char* ev = getenv("APSS_RANGE_ROWS")) {
+    const int rr = atoi(ev);
+    if (rr >= CB) K = rr / CB;
+  }
+  const int64_t nR = (nb + K - 1) / K;
+  const int64_t range_rows = (int64_t)K * CB;
+  if (!ix->toff.p || ix->toff_rows != range_rows) {
+    CHK(ix->toff.alloc((nR + 1) * std::max<int64_t>(ix->m - ix->H, 1)), "alloc range offsets");
+    CHK(launch_range_offsets(ix->off.p, ix->post.p, ix->H, ix->m, nR, range_rows, ix->toff.p, s), "range offsets");
+    ix->toff_rows = range_rows;
+    ix->toff_nR = nR;
+  }
+  const int64_t ntiles = (Q.n + QT - 1) / QT;
+  const int64_t nrx = (nR + 7) / 8;
+  std::vector<int64_t> cum((size_t)(8 * (nrx + 1)), 0);
+  for (int x = 0; x < 8; ++x) {
+    int64_t c = 0;
+    for (int64_t j = 0; j <= nrx; ++j) {
+      cum[(size_t)(x * (nrx + 1) + j)] = c;
+      const int64_t R = x + 8 * j;
+      if (j < nrx && R < nR) {
+        const int64_t tmin = triangle ? std::min<int64_t>(ntiles, (R * range_rows) / QT) : 0;
+        c += ntiles - tmin;
+      }
+    }
+  }
+  CHK(ix->qcum.reserve((int64_t)cum.size()), "alloc queues");
+  CHK(hipMemcpyAsync(ix->qcum.p, cum.data(), sizeof(int64_t) * cum.size(), hipMemcpyHostToDevice, s), "queues");
+  CHK(ix->qctr.reserve(8), "alloc queues");
   CHK(ix->counters.reserve(C_NUM), "alloc counters");
+  if (!ix->grid[variant]) ix->grid[variant] = join_resident_groups(variant);
+  const int G = ix->grid[variant];
+  // per-workgroup cursor space for tiles too large to stage in LDS
+  CHK(ix->scalar.reserve(1), "alloc");
+  CHK(fill_u64((uint64_t*)ix->scalar.p, 0ull, 1, s), "fill");
+  CHK(launch_max_tile_nnz(Q.rp, Q.n, QT, ix->scalar.p, s), "tile sizes");
+  unsigned long long maxtile = 0;
+  CHK(hipMemcpyAsync(&maxtile, ix->scalar.p, sizeof(maxtile), hipMemcpyDeviceToHost, s), "tile sizes");
+  CHK(hipStreamSynchronize(s), "tile sizes");
+  const int64_t wg_stride = 2 * (int64_t)std::max<unsigned long long>(maxtile, 1);
+  CHK(ix->wg_cur.reserve((int64_t)G * wg_stride), "alloc cursors");
   if (!ix->raw_key.p) {
     const int64_t cap0 = std::max<int64_t>(1 << 20, 16 * std::max(ix->n, Q.n));
     CHK(ix->raw_key.alloc(cap0), "alloc pairs");
@@ -388,6 +441,7 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
   for (int attempt = 0; attempt < 2; ++attempt) {
     CHK(hipEventRecord(ix->ev[0], s), "event");
     CHK(fill_u64((uint64_t*)ix->counters.p, 0ull, C_NUM, s), "fill");
+    CHK(fill_u32(ix->qctr.p, 0u, 8, s), "fill");
     JoinArgs a;
     a.rp = ix->rows.rp.p;
     a.rc = ix->rows.rc.p;
@@ -395,9 +449,10 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     a.off = ix->off.p;
     a.post = ix->post.p;
     a.post4 = ix->post4.p;
-    a.hoff = ix->hoff[hoff_slot(CB)].p;
+    a.post4_bytes = (uint32_t)(4 * (ix->P + 1));
+    a.hoff = ix->hoff[slot].p;
     a.H = ix->H;
-    a.nb = ix->hoff_nb[hoff_slot(CB)];
+    a.nb = nb;
     a.n = ix->n;
     a.qrp = Q.rp;
     a.qrc = Q.rc;
@@ -406,16 +461,26 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     a.t = t;
     a.nq = Q.n;
     a.triangle = triangle;
-    a.cur_pos = ix->cur_pos.p;
-    a.cur_ny = ix->cur_ny.p;
-    a.ntiles = (Q.n + QT - 1) / QT;
+    a.ntiles = ntiles;
+    a.toff = ix->toff.p;
+    a.m_tail = (int32_t)(ix->m - ix->H);
+    a.K = K;
+    a.nrx = nrx;
+    a.qcum = ix->qcum.p;
+    a.qctr = ix->qctr.p;
+    a.wg_cur = ix->wg_cur.p;
+    a.wg_cur_stride = wg_stride;
     a.out_key = ix->raw_key.p;
     a.out_sim = ix->raw_sim.p;
     a.cap = ix->raw_key.n;
     a.bj = bj;
     a.counters = ix->counters.p;
     CHK(hipEventRecord(ix->ev[1], s), "event");
-    CHK(launch_join(a, variant, s), "join kernel");
+    if (!join_args_complete(a)) {
+      set_error("internal: join launched with a missing device buffer");
+      return APSS_EDEVICE;
+    }
+    CHK(launch_join(a, variant, G, s), "join kernel");
     CHK(hipEventRecord(ix->ev[2], s), "event");
     unsigned long long c[C_NUM];
     CHK(hipMemcpyAsync(c, ix->counters.p, sizeof(c), hipMemcpyDeviceToHost, s), "read counters");
@@ -625,7 +690,7 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
   ix->n = n;
   ix->m = m;
   ix->t_build = t_build;
-  ix->variant = o.variant >= 0 ? o.variant : 0;
+  ix->variant = o.variant >= 0 ? o.variant : 1;
   if (const char* ev = getenv("APSS_VARIANT")) {
     const int v = atoi(ev);
     if (v >= 0 && v < join_num_variants()) ix->variant = v;

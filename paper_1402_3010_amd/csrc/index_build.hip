@@ -8,8 +8,6 @@
 //                                     the leading components with b < t are x'
 //  k_count_indexed / k_emit_indexed   inverted lists of the indexed parts, by vector id
 //  k_block_offsets                    where each dense list enters each corpus block
-#include <hip/hip_fp16.h>
-
 #include "apss_internal.h"
 #include "index_build.h"
 
@@ -181,14 +179,15 @@ __global__ void k_unpack_post(const uint64_t* __restrict__ vals, int64_t P, Post
 }
 
 // Packed copy of the list entries for streaming: low 16 bits = vector id mod
-// 2^16, high 16 bits = the weight as an IEEE half rounded toward +inf (the
-// next half up when round-to-nearest fell below the weight).
+// 2^16 (its offset inside any power-of-two block), high 16 bits = the weight
+// in units of 2^-15 rounded up (w * 2^15 is exact in float, so the ceiling is
+// the smallest such unit count not below w).
 __global__ void k_pack_post4(const Post* __restrict__ post, int64_t P, uint32_t* __restrict__ post4) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
     const Post p = post[k];
-    unsigned short h = __half_as_ushort(__float2half_rn(p.w));
-    if (__half2float(__ushort_as_half(h)) < p.w) ++h;
-    post4[k] = (p.y & 0xFFFFu) | ((uint32_t)h << 16);
+    uint32_t w15 = (uint32_t)ceilf(p.w * 32768.0f);
+    if (w15 > 0xFFFFu) w15 = 0xFFFFu;
+    post4[k] = (p.y & 0xFFFFu) | (w15 << 16);
   }
 }
 

@@ -12,7 +12,8 @@ struct JoinArgs {
   const RowStat* rs;      // [n]
   const int64_t* off;     // [m+1] list offsets by rank
   const Post* post;       // [P]   list entries, vector ids ascending within a list
-  const uint32_t* post4;  // [P]   the same entries packed: id mod 2^16 | half weight (rounded up) << 16
+  const uint32_t* post4;  // [P+1] the same entries packed: id mod 2^16 | weight in 2^-15 units (rounded up) << 16
+  uint32_t post4_bytes;   // size of post4 in bytes (< 2^32)
   const uint32_t* hoff;   // [(nb+1) * H] first entry of list r at or after block b
   int32_t H;              // ranks with block offsets
   int64_t nb;             // corpus blocks
@@ -25,9 +26,16 @@ struct JoinArgs {
   float t;                // threshold when qt is NULL
   int64_t nq;
   int32_t triangle;       // 1: self-join, query q only meets corpus rows y < q
-  uint32_t* cur_pos;      // [qnnz] list cursors of tiles too large to stage in LDS
-  uint32_t* cur_ny;       // [qnnz] vector id at each such cursor
   int64_t ntiles;
+  // work items (corpus range of K blocks, query tile), queued per XCD
+  const uint32_t* toff;   // [(nR+1) * m_tail] first entry of sparse list H + rt at or after range R
+  int32_t m_tail;         // m - H
+  int32_t K;              // blocks per range
+  int64_t nrx;            // range slots per XCD queue
+  const int64_t* qcum;    // [8 * (nrx+1)] cumulative item counts of queue x's ranges x, x+8, ...
+  unsigned int* qctr;     // [8] next item of each queue (zero at launch)
+  uint32_t* wg_cur;       // per-workgroup cursors of tiles too large to stage in LDS
+  int64_t wg_cur_stride;  // 2 * largest tile's component count
   // output
   uint64_t* out_key;      // [cap] (i << bj) | j
   float* out_sim;         // [cap]
@@ -36,10 +44,21 @@ struct JoinArgs {
   unsigned long long* counters;  // [C_NUM]
 };
 
+// True when every device buffer the join kernel dereferences is present.
+inline bool join_args_complete(const JoinArgs& a) {
+  return a.rp && a.rc && a.rs && a.off && a.post && a.post4 && a.hoff && a.qrp && a.qrc && a.qmw && a.toff &&
+         a.qcum && a.qctr && a.wg_cur && a.out_key && a.out_sim && a.counters;
+}
+
 // Compiled tile variants of the join kernel.
 int join_num_variants();
 int join_variant_geometry(int variant, int* queries_per_tile, int* block_rows);
-hipError_t launch_join(const JoinArgs& a, int variant, hipStream_t s);
+hipError_t launch_join(const JoinArgs& a, int variant, int grid, hipStream_t s);
+// Workgroups of a variant that fit on the device at once.
+int join_resident_groups(int variant);
+hipError_t launch_range_offsets(const int64_t* off, const Post* post, int32_t H, int64_t m, int64_t nR,
+                                int64_t range_rows, uint32_t* toff, hipStream_t s);
+hipError_t launch_max_tile_nnz(const int64_t* qrp, int64_t nq, int qt, unsigned long long* out, hipStream_t s);
 hipError_t launch_unpack_pairs(const uint64_t* keys, const float* sim, int64_t cnt, int bj, uint32_t* oi,
                                uint32_t* oj, float* os, hipStream_t s);
 

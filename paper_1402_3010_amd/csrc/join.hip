@@ -27,8 +27,6 @@
 //     lane-strided order and a fixed butterfly, so the result depends only on
 //     (q, y); if it lies within kBand of t the pair is decided by a double
 //     rescore.  Emitted pairs are compacted per wave (ballot + prefix).
-#include <hip/hip_fp16.h>
-
 #include "apss_internal.h"
 #include "join.h"
 
@@ -40,11 +38,20 @@ namespace {
 // scaled value is exact in float and below 2^30 + 1)
 __device__ __forceinline__ uint32_t fixp(float a, float b) { return (uint32_t)ceilf(__fmul_rn(a, b) * kFix); }
 
-// Weight of a packed list entry: bits 16..31 hold the weight as an IEEE
-// half rounded up, so accumulated scores only over-estimate (bits 0..15 hold
-// the vector id modulo 2^16, its offset inside any power-of-two block).
-__device__ __forceinline__ float w16(uint32_t e) {
-  return __half2float(__ushort_as_half((unsigned short)(e >> 16)));
+// Query weight in units of 2^-15, rounded up.  A packed list entry holds the
+// corpus weight in the same units (bits 16..31, rounded up) and the vector id
+// modulo 2^16 (bits 0..15), so the product of the two 15-bit counts is an
+// upper bound of q_d * y_d in units of 2^-30, computed by one 24-bit multiply.
+__device__ __forceinline__ uint32_t q15(float w) {
+  const uint32_t v = (uint32_t)ceilf(w * 32768.0f);
+  return v > 0xFFFFu ? 0xFFFFu : v;
+}
+__device__ __forceinline__ uint32_t packed_product(uint32_t q, uint32_t e) { return __umul24(q, e >> 16); }
+
+// Buffer descriptor of a device array (gfx9 resource word 3); loads through it
+// take a scalar base offset and are bounds-checked by the hardware.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
 }
 
 // segments at least this long are streamed by a whole wave
@@ -66,11 +73,11 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 }
 
 // One dense-list segment of a (tile, block): list positions [pos, pos + len)
-// feed query slot qi with weight w.  lenq = len | qi << 16.
+// feed query slot qi with the query weight q (units of 2^-15).  lenq = len | qi << 16.
 struct Seg {
   uint32_t pos;
   uint32_t lenq;
-  float w;
+  uint32_t q;
 };
 
 template <int QT_, int CB_, int NT_, int RD_, int SQ_, int QB_, int U_, int UL_, int WPE_>
@@ -107,6 +114,7 @@ struct Smem {
   int32_t lnext;   // next long segment to hand out
   int32_t qcount;
   int32_t ovf;
+  int64_t item;
   unsigned long long cnt[C_NUM];
 };
 
@@ -124,7 +132,37 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   const int wave = uni(tid >> 6);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  const int64_t tile = a.ntiles - 1 - (int64_t)blockIdx.x;  // heaviest tiles first
+  unsigned long long c_visit = 0, c_tail = 0, c_cand = 0, c_surv = 0, c_ver = 0, c_band = 0;
+  uint64_t vis_u = 0;  // visits of long segments, counted per wave (uniform)
+  if (tid < C_NUM) sm.cnt[tid] = 0;
+  const __amdgpu_buffer_rsrc_t prs = make_rsrc(a.post4, a.post4_bytes);
+  // the accumulators start at zero and every item leaves them at zero
+  for (int e = tid; e < QT * CB; e += NT) sm.acc[e] = 0u;
+
+  // Persistent loop over work items (corpus range R, query tile T).  The
+  // queue of XCD x holds the ranges R = x, x + 8, ... in order, so the
+  // workgroups resident on one XCD share one range of lists in its L2;
+  // an XCD whose queue is empty takes items from the others.
+  const int xcd = (int)(blockIdx.x & 7u);
+  for (int qx = 0; qx < 8; ++qx) {
+    const int x = (xcd + qx) & 7;
+    const int64_t* cum = a.qcum + (int64_t)x * (a.nrx + 1);
+    const int64_t total = cum[a.nrx];
+    for (;;) {
+      __syncthreads();
+      if (tid == 0) sm.item = (int64_t)atomicAdd(&a.qctr[x], 1u);
+      __syncthreads();
+      const int64_t it = uni64(sm.item);
+      if (it >= total) break;
+      int lo_j = 0, hi_j = (int)a.nrx - 1;  // range slot j with cum[j] <= it < cum[j + 1]
+      while (lo_j < hi_j) {
+        const int mid = (lo_j + hi_j + 1) >> 1;
+        if (cum[mid] <= it) lo_j = mid;
+        else hi_j = mid - 1;
+      }
+      const int64_t R = (int64_t)x + 8 * (int64_t)lo_j;
+      const int64_t tile = a.ntiles - 1 - (it - cum[lo_j]);
+      const int64_t b_begin = R * a.K;
   const int64_t q0 = tile * QT;
   const int qn = (int)((a.nq - q0) < QT ? (a.nq - q0) : QT);
 
@@ -133,7 +171,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     sm.qmw[tid] = tid < qn ? a.qmw[q0 + tid] : 0.0f;
     sm.qt[tid] = (tid < qn && a.qt) ? a.qt[q0 + tid] : a.t;
   }
-  if (tid < C_NUM) sm.cnt[tid] = 0;
   if (tid == 0) {
     sm.nseg = 0;
     sm.nshort = 0;
@@ -142,7 +179,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     sm.ovf = 0;
   }
   for (int e = tid; e < QT * RD; e += NT) sm.qd[e] = 0.0f;
-  for (int e = tid; e < QT * CB; e += NT) sm.acc[e] = 0u;
   __syncthreads();
   const int64_t qbase = uni64(sm.qoff[0]);
   const int64_t tile_nnz = uni64(sm.qoff[qn]) - qbase;
@@ -165,31 +201,40 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   };
   int64_t last_b = -1;
   if (qn > 0 && a.n > 0) last_b = a.triangle ? (q0 + qn - 1) / CB : (a.nb - 1);
+  const int64_t b_end = (b_begin + a.K) < (last_b + 1) ? (b_begin + a.K) : (last_b + 1);
+  uint32_t* const gcur = a.wg_cur + (int64_t)blockIdx.x * a.wg_cur_stride;  // cursors of unstaged tiles
 
   // stage the tile, fill the dense lookup table, place every list cursor at
-  // its list start, and fetch block 0's segment ends of the dense lists
+  // the range's first block (block offsets for dense lists, range offsets
+  // for sparse ones), and fetch that block's segment ends of the dense lists
   uint32_t hn[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) hn[j] = 0;
-  for (int64_t k = tid; k < tile_nnz; k += NT) {
-    const RComp c = a.qrc[qbase + k];
-    const int qi = find_slot(qbase + k);
-    if (c.r < RD) sm.qd[qi * RD + c.r] = c.w;
-    const int64_t p0 = a.off[c.r];
-    uint32_t ny = 0;
-    if (c.r >= a.H) ny = p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
-    if (staged) {
-      sm.qrow[k] = c;
-      sm.cqi[k] = (uint8_t)qi;
-      sm.cur[k] = make_uint2((uint32_t)p0, ny);
-      if (c.r < a.H && last_b >= 0) {
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j)
-          if (k == (int64_t)j * NT + tid) hn[j] = a.hoff[(int64_t)a.H + c.r];
+  if (b_begin < b_end) {
+    for (int64_t k = tid; k < tile_nnz; k += NT) {
+      const RComp c = a.qrc[qbase + k];
+      const int qi = find_slot(qbase + k);
+      if (c.r < RD) sm.qd[qi * RD + c.r] = c.w;
+      uint32_t p0, ny = 0;
+      if (c.r < a.H) {
+        p0 = a.hoff[b_begin * (int64_t)a.H + c.r];
+      } else {
+        p0 = a.toff[R * (int64_t)a.m_tail + (c.r - a.H)];
+        ny = (int64_t)p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
       }
-    } else {
-      a.cur_pos[qbase + k] = (uint32_t)p0;
-      a.cur_ny[qbase + k] = ny;
+      if (staged) {
+        sm.qrow[k] = c;
+        sm.cqi[k] = (uint8_t)qi;
+        sm.cur[k] = make_uint2(p0, ny);
+        if (c.r < a.H) {
+#pragma unroll
+          for (int j = 0; j < KMAX; ++j)
+            if (k == (int64_t)j * NT + tid) hn[j] = a.hoff[(b_begin + 1) * (int64_t)a.H + c.r];
+        }
+      } else {
+        gcur[2 * k] = p0;
+        gcur[2 * k + 1] = ny;
+      }
     }
   }
   __syncthreads();
@@ -207,9 +252,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     return (lo < sm.qlen[qi] && row[lo].r == r) ? row[lo].w : 0.0f;
   };
 
-  unsigned long long c_visit = 0, c_tail = 0, c_cand = 0, c_surv = 0, c_ver = 0, c_band = 0;
 
-  for (int64_t b = 0; b <= last_b; ++b) {
+  for (int64_t b = b_begin; b < b_end; ++b) {
     const int64_t blk0 = b * CB;
     const int64_t blk1 = (blk0 + CB) < a.n ? (blk0 + CB) : a.n;
     const uint32_t* hend = a.hoff + (b + 1) * (int64_t)a.H;   // end of each dense list's block segment
@@ -242,7 +286,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       for (int j = 0; j < KMAX; ++j) {
         const int64_t k = cb + (int64_t)j * NT + tid;
         bool has_seg = false;
-        Seg sg = {0u, 0u, 0.0f};
+        Seg sg = {0u, 0u, 0u};
         thit[j] = false;
         tpos[j] = 0;
         tend[j] = 0;
@@ -261,14 +305,14 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           } else {
             c = a.qrc[qbase + k];
             qi = find_slot(qbase + k);
-            pos = a.cur_pos[qbase + k];
-            ny = a.cur_ny[qbase + k];
+            pos = gcur[2 * k];
+            ny = gcur[2 * k + 1];
           }
           if (c.r < a.H) {
             uint32_t e;
             if (staged) {
               e = hn[j];
-              if (b < last_b) hn[j] = hnext[c.r];  // prefetch for the next block
+              if (b + 1 < b_end) hn[j] = hnext[c.r];  // prefetch for the next block
             } else {
               e = hend[c.r];
             }
@@ -276,9 +320,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
               has_seg = true;
               sg.pos = pos;
               sg.lenq = (e - pos) | ((uint32_t)qi << 16);
-              sg.w = c.w;
+              sg.q = q15(c.w);
               if (staged) sm.cur[k] = make_uint2(e, 0u);
-              else a.cur_pos[qbase + k] = e;
+              else gcur[2 * k] = e;
             }
           } else if ((int64_t)ny < blk1) {
             thit[j] = true;
@@ -328,8 +372,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           if (staged) {
             sm.cur[k] = make_uint2(pos, ny);
           } else {
-            a.cur_pos[qbase + k] = pos;
-            a.cur_ny[qbase + k] = ny;
+            gcur[2 * k] = pos;
+            gcur[2 * k + 1] = ny;
           }
         }
       }
@@ -386,7 +430,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             else hi = mid - 1;
           }
           int s = lo, cs = -1, pre = 0;
-          Seg S = {0u, 0u, 0.0f};
+          Seg S = {0u, 0u, 0u};
           for (int base = vbeg; base < vend; base += 64 * U) {
             // resolve every visit's segment first (LDS only), then issue all
             // list loads back to back with clamped addresses, then accumulate
@@ -403,16 +447,15 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
                 cs = s;
               }
               pos[u] = S.pos + (uint32_t)(v - pre);
-              qwb[u] = __float_as_uint(S.w);
+              qwb[u] = S.q;
               qs[u] = vr < vend ? (int)(S.lenq >> 16) : -1;
             }
             uint32_t p[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) p[u] = a.post4[pos[u]];
+            for (int u = 0; u < U; ++u) p[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, (int)(pos[u] * 4u), 0, 0);
 #pragma unroll
             for (int u = 0; u < U; ++u)
-              if (qs[u] >= 0)
-                atomicAdd(&sm.acc[qs[u] * CB + (int)(p[u] & (CB - 1))], fixp(__uint_as_float(qwb[u]), w16(p[u])));
+              if (qs[u] >= 0) atomicAdd(&sm.acc[qs[u] * CB + (int)(p[u] & (CB - 1))], packed_product(qwb[u], p[u]));
           }
         }
       }
@@ -421,25 +464,23 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       // possibly from different segments, are loaded before accumulating
       {
         int si = wave, off = 0;
-        uint32_t spos = 0, slenq = 0;
-        float sw = 0.0f;
+        uint32_t spos = 0, slenq = 0, sq = 0;
         int cur_si = -1;
         while (si < nl) {
-          uint32_t cpos[UL];
+          uint32_t cpos[UL], cq[UL];
           int ccnt[UL], cab[UL];
-          float cw[UL];
 #pragma unroll
           for (int u = 0; u < UL; ++u) {
             ccnt[u] = 0;
             cpos[u] = 0;
             cab[u] = 0;
-            cw[u] = 0.0f;
+            cq[u] = 0;
             if (si < nl) {
               if (si != cur_si) {
                 const Seg S = sm.seg[si];
                 spos = __builtin_amdgcn_readfirstlane(S.pos);
                 slenq = __builtin_amdgcn_readfirstlane(S.lenq);
-                sw = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(S.w))) * kFix;
+                sq = __builtin_amdgcn_readfirstlane(S.q);
                 cur_si = si;
               }
               const int len = (int)(slenq & 0xFFFFu);
@@ -447,7 +488,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
               ccnt[u] = left < 64 ? left : 64;
               cpos[u] = spos + (uint32_t)off;
               cab[u] = (int)(slenq >> 16) * CB;
-              cw[u] = sw;
+              cq[u] = sq;
               off += 64;
               if (off >= len) {
                 off = 0;
@@ -455,19 +496,17 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
               }
             }
           }
-          // unconditional loads (an empty slot re-reads a valid entry) keep the
-          // U loads back to back
+          // one buffer load per chunk: scalar base, lane offset; lanes past
+          // the chunk read other entries (or zeros past the array) and are
+          // masked below
           uint32_t p[UL];
 #pragma unroll
-          for (int u = 0; u < UL; ++u) {
-            const int li = lane < ccnt[u] ? lane : (ccnt[u] > 0 ? ccnt[u] - 1 : 0);
-            p[u] = a.post4[(ccnt[u] > 0 ? cpos[u] : cpos[0]) + (uint32_t)li];
-          }
+          for (int u = 0; u < UL; ++u) p[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, lane * 4, (int)(cpos[u] * 4u), 0);
 #pragma unroll
           for (int u = 0; u < UL; ++u) {
             if (ccnt[u] > 0) {
-              if (lane == 0) c_visit += (unsigned long long)ccnt[u];
-              if (lane < ccnt[u]) atomicAdd(&sm.acc[cab[u] + (int)(p[u] & (CB - 1))], (uint32_t)ceilf(cw[u] * w16(p[u])));
+              vis_u += (uint32_t)ccnt[u];
+              if (lane < ccnt[u]) atomicAdd(&sm.acc[cab[u] + (int)(p[u] & (CB - 1))], packed_product(cq[u], p[u]));
             }
           }
         }
@@ -627,7 +666,12 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     }
   }
 
+    }  // items of queue x
+  }    // queues
+
   // ------------------------------------------------------------ counters
+  __syncthreads();
+  if (lane == 0) c_visit += vis_u;
   atomicAdd(&sm.cnt[C_VISITS], c_visit);
   atomicAdd(&sm.cnt[C_TAILVISITS], c_tail);
   atomicAdd(&sm.cnt[C_CANDIDATES], c_cand);
@@ -636,6 +680,34 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   atomicAdd(&sm.cnt[C_BAND], c_band);
   __syncthreads();
   if (tid < C_NUM && tid != C_MATCHES && sm.cnt[tid]) atomicAdd(&a.counters[tid], sm.cnt[tid]);
+}
+
+// toff[R * (m - H) + (r - H)] = first position in sparse list r whose vector
+// id is >= R * range_rows.
+__global__ void k_range_offsets(const int64_t* __restrict__ off, const Post* __restrict__ post, int32_t H, int64_t m,
+                                int64_t nR, int64_t range_rows, uint32_t* __restrict__ toff) {
+  const int64_t mt = m - H;
+  const int64_t total = (nR + 1) * mt;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t R = e / mt;
+    const int64_t r = H + (e - R * mt);
+    int64_t lo = off[r], hi = off[r + 1];
+    const uint64_t y0 = (uint64_t)R * (uint64_t)range_rows;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((uint64_t)post[mid].y < y0) lo = mid + 1;
+      else hi = mid;
+    }
+    toff[e] = (uint32_t)lo;
+  }
+}
+
+__global__ void k_max_tile_nnz(const int64_t* __restrict__ qrp, int64_t nq, int qt, unsigned long long* __restrict__ out) {
+  const int64_t nt = (nq + qt - 1) / qt;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = (t + 1) * qt < nq ? (t + 1) * qt : nq;
+    atomicMax(out, (unsigned long long)(qrp[e] - qrp[t * qt]));
+  }
 }
 
 __global__ void k_unpack_pairs(const uint64_t* __restrict__ keys, const float* __restrict__ sim, int64_t cnt, int bj,
@@ -686,20 +758,58 @@ int join_variant_geometry(int v, int* qt, int* cb) {
 }
 
 template <class C>
-hipError_t launch_variant(const JoinArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_join<C>), dim3((unsigned)a.ntiles), dim3(C::NT), 0, s, a);
+hipError_t launch_variant(const JoinArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_join<C>), dim3((unsigned)grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_join(const JoinArgs& a, int variant, hipStream_t s) {
-  if (a.ntiles <= 0) return hipSuccess;
+hipError_t launch_join(const JoinArgs& a, int variant, int grid, hipStream_t s) {
+  if (a.ntiles <= 0 || grid <= 0) return hipSuccess;
   switch (variant) {
-    case 0: return launch_variant<V0>(a, s);
-    case 1: return launch_variant<V1>(a, s);
-    case 2: return launch_variant<V2>(a, s);
-    case 3: return launch_variant<V3>(a, s);
+    case 0: return launch_variant<V0>(a, grid, s);
+    case 1: return launch_variant<V1>(a, grid, s);
+    case 2: return launch_variant<V2>(a, grid, s);
+    case 3: return launch_variant<V3>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <class C>
+int resident(int cus) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_join<C>), C::NT, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * cus;
+}
+
+int join_resident_groups(int variant) {
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  switch (variant) {
+    case 0: return resident<V0>(cus);
+    case 1: return resident<V1>(cus);
+    case 2: return resident<V2>(cus);
+    case 3: return resident<V3>(cus);
+    default: return cus;
+  }
+}
+
+hipError_t launch_range_offsets(const int64_t* off, const Post* post, int32_t H, int64_t m, int64_t nR,
+                                int64_t range_rows, uint32_t* toff, hipStream_t s) {
+  const int64_t total = (nR + 1) * (m - H);
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_range_offsets, dim3(grid(total)), dim3(256), 0, s, off, post, H, m, nR, range_rows, toff);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_tile_nnz(const int64_t* qrp, int64_t nq, int qt, unsigned long long* out, hipStream_t s) {
+  const int64_t nt = (nq + qt - 1) / qt;
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_max_tile_nnz, dim3(grid(nt)), dim3(256), 0, s, qrp, nq, qt, out);
+  return hipGetLastError();
 }
 
 }  // namespace apss

@@ -265,12 +265,14 @@ hipError_t radix_sort_u64_u32(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, ui
 
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  if (!p) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
   return hipGetLastError();
 }
 
 hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  if (!p) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
   return hipGetLastError();
 }
