@@ -37,7 +37,7 @@ def cpu_baseline(V, t, budget_s: float):
     corpus, each matched against every earlier row; sized to ~budget_s.
 
     Each oracle call first builds the full inverted index (a fixed cost), so
-    the row count is chosen from two probe runs (time = fixed + rows * per_row).
+    the row count is scaled from one probe whose time includes that cost.
     """
     import oracle
     n = V.n
@@ -47,21 +47,22 @@ def cpu_baseline(V, t, budget_s: float):
         r = oracle.join_plain(V, t, n - rows, n)
         return r, time.perf_counter() - t0
 
-    p1, p2 = min(n, 16), min(n, 128)
-    _, d1 = run(p1)
-    _, d2 = run(p2)
-    per_row = max((d2 - d1) / max(p2 - p1, 1), 1e-6)
-    fixed = max(d1 - per_row * p1, 0.0)
-    rows = int(min(n, max(p2, (budget_s - fixed) / per_row)))
+    # one probe; scaling its time (which includes the fixed cost) can only
+    # over-estimate the per-row cost, so the sample stays within the budget
+    probe = min(n, 256)
+    _, dp = run(probe)
+    log("cpu baseline: probe of %d rows took %.2f s" % (probe, dp))
+    rows = int(min(n, max(probe, probe * budget_s / max(dp, 1e-3))))
     r, dt = run(rows)
+    log("cpu baseline: %d rows took %.2f s" % (rows, dt))
     return {
         "value": r.candidates / dt,
         "unit": "candidate pairs scored/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": "rows %d..%d of the same corpus, each against all earlier rows: %d candidate pairs, "
-                  "%d matches in %.1f s (includes building the full inverted index, %.1f s)"
-                  % (n - rows, n - 1, r.candidates, len(r), dt, fixed),
+                  "%d matches in %.1f s (includes building the full inverted index)"
+                  % (n - rows, n - 1, r.candidates, len(r), dt),
         "matches_per_s": len(r) / dt,
         "posting_visits_per_s": r.visits / dt,
     }
@@ -77,7 +78,20 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="fewer rows (same distributions), for quick checks")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (3 times), to calibrate "
+                         "the FETCH_SIZE / WRITE_SIZE counters against a known byte count")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the join runs on a single MI355X; "
               "multi-GPU sharding is not built (see DESIGN.md)", file=sys.stderr)

@@ -132,7 +132,9 @@ struct apss_index {
   // range offsets of the sparse lists for one range width (rows)
   DBuf<uint32_t> toff;
   int64_t toff_rows = 0, toff_nR = 0;
+  std::vector<int64_t> rp_host;  // host copy of the corpus row offsets
   // join workspace
+  DBuf<int64_t> tstart;
   DBuf<uint32_t> wg_cur;
   DBuf<int64_t> qcum;
   DBuf<unsigned int> qctr;
@@ -300,6 +302,8 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   ix->rows.nnz = nnz;
   CHK(ix->rows.rp.alloc(n + 1), "alloc");
   CHK(hipMemcpyAsync(ix->rows.rp.p, in.prp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s), "copy");
+  ix->rp_host.resize((size_t)n + 1);
+  CHK(hipMemcpyAsync(ix->rp_host.data(), in.prp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s), "copy");
   CHK(ix->rows.rc.alloc(nnz), "alloc");
   if ((rc = sort_rows(ix, ss.k1.p, ss.v32a.p, nnz, nbits + rbits, rbits, ix->rows.rc.p, err.p))) return rc;
   if ((rc = check_err(ix, err.p, nullptr, "build_index"))) return rc;
@@ -363,11 +367,38 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
 }
 
 struct QuerySet {
-  const int64_t* rp;
+  const int64_t* rp;       // device
   const RComp* rc;
   const float* mw;
   int64_t n, nnz;
+  const int64_t* rp_host;  // host copy of rp
 };
+
+// Query tiles: consecutive queries, at most QT of them and, unless a single
+// query is larger, at most QB components, so that a tile fits the LDS staging.
+struct Tiles {
+  std::vector<int64_t> start;  // ntiles + 1 entries
+  int64_t max_nnz = 0;
+};
+
+Tiles make_tiles(const int64_t* rp, int64_t n, int QT, int QB) {
+  Tiles T;
+  T.start.push_back(0);
+  int64_t nnz = 0;
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t len = rp[q + 1] - rp[q];
+    const int64_t cur = T.start.back();
+    if (q > cur && (q - cur == QT || nnz + len > QB)) {
+      T.max_nnz = std::max(T.max_nnz, nnz);
+      T.start.push_back(q);
+      nnz = 0;
+    }
+    nnz += len;
+  }
+  T.max_nnz = std::max(T.max_nnz, nnz);
+  T.start.push_back(n);
+  return T;
+}
 
 // Run the join kernels; raw (unsorted) pairs in ix->raw_key / raw_sim, count in *count.
 int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const float* qt_dev, int64_t* count) {
@@ -402,7 +433,11 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     ix->toff_rows = range_rows;
     ix->toff_nR = nR;
   }
-  const int64_t ntiles = (Q.n + QT - 1) / QT;
+  const Tiles tiles = make_tiles(Q.rp_host, Q.n, QT, join_variant_staging(variant));
+  const int64_t ntiles = (int64_t)tiles.start.size() - 1;
+  CHK(ix->tstart.reserve(ntiles + 1), "alloc tiles");
+  CHK(hipMemcpyAsync(ix->tstart.p, tiles.start.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, s),
+      "tiles");
   const int64_t nrx = (nR + 7) / 8;
   std::vector<int64_t> cum((size_t)(8 * (nrx + 1)), 0);
   for (int x = 0; x < 8; ++x) {
@@ -411,7 +446,11 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
       cum[(size_t)(x * (nrx + 1) + j)] = c;
       const int64_t R = x + 8 * j;
       if (j < nrx && R < nR) {
-        const int64_t tmin = triangle ? std::min<int64_t>(ntiles, (R * range_rows) / QT) : 0;
+        // first tile whose last query reaches the range (self-join triangle)
+        const int64_t tmin =
+            triangle ? (int64_t)(std::upper_bound(tiles.start.begin() + 1, tiles.start.end(), R * range_rows) -
+                                 (tiles.start.begin() + 1))
+                     : 0;
         c += ntiles - tmin;
       }
     }
@@ -423,13 +462,7 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
   if (!ix->grid[variant]) ix->grid[variant] = join_resident_groups(variant);
   const int G = ix->grid[variant];
   // per-workgroup cursor space for tiles too large to stage in LDS
-  CHK(ix->scalar.reserve(1), "alloc");
-  CHK(fill_u64((uint64_t*)ix->scalar.p, 0ull, 1, s), "fill");
-  CHK(launch_max_tile_nnz(Q.rp, Q.n, QT, ix->scalar.p, s), "tile sizes");
-  unsigned long long maxtile = 0;
-  CHK(hipMemcpyAsync(&maxtile, ix->scalar.p, sizeof(maxtile), hipMemcpyDeviceToHost, s), "tile sizes");
-  CHK(hipStreamSynchronize(s), "tile sizes");
-  const int64_t wg_stride = 2 * (int64_t)std::max<unsigned long long>(maxtile, 1);
+  const int64_t wg_stride = 2 * std::max<int64_t>(tiles.max_nnz, 1);
   CHK(ix->wg_cur.reserve((int64_t)G * wg_stride), "alloc cursors");
   if (!ix->raw_key.p) {
     const int64_t cap0 = std::max<int64_t>(1 << 20, 16 * std::max(ix->n, Q.n));
@@ -462,6 +495,7 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     a.nq = Q.n;
     a.triangle = triangle;
     a.ntiles = ntiles;
+    a.tstart = ix->tstart.p;
     a.toff = ix->toff.p;
     a.m_tail = (int32_t)(ix->m - ix->H);
     a.K = K;
@@ -584,6 +618,7 @@ int finish_host(apss_index* ix, int64_t cnt, int bj, apss_pairs* out) {
 struct QueryStage {
   RankRows rows;
   DBuf<float> qt;
+  std::vector<int64_t> rp_host;
 };
 
 int stage_queries(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col, const float* q_val,
@@ -618,6 +653,8 @@ int stage_queries(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, const in
   qs.rows.nnz = nnz;
   CHK(qs.rows.rp.alloc(nq + 1), "alloc");
   CHK(hipMemcpyAsync(qs.rows.rp.p, in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToDevice, s), "copy");
+  qs.rp_host.resize((size_t)nq + 1);
+  CHK(hipMemcpyAsync(qs.rp_host.data(), in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s), "copy");
   CHK(qs.rows.rc.alloc(nnz), "alloc");
   CHK(qs.rows.mw.alloc(nq), "alloc");
   SortScratch& ss = ix->ss;
@@ -722,7 +759,7 @@ int apss_join_device(apss_index* ix, float t, uint32_t* out_i, uint32_t* out_j, 
   }
   int rc = check_t(ix, t);
   if (rc) return rc;
-  QuerySet Q{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz};
+  QuerySet Q{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz, ix->rp_host.data()};
   int64_t cnt = 0;
   if ((rc = run_join(ix, Q, 1, t, nullptr, &cnt))) return rc;
   return finish_device(ix, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count);
@@ -738,7 +775,7 @@ int apss_join(apss_index* ix, float t, apss_pairs* out) {
   out->sim = nullptr;
   int rc = check_t(ix, t);
   if (rc) return rc;
-  QuerySet Q{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz};
+  QuerySet Q{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz, ix->rp_host.data()};
   int64_t cnt = 0;
   if ((rc = run_join(ix, Q, 1, t, nullptr, &cnt))) return rc;
   return finish_host(ix, cnt, ceil_log2((uint64_t)ix->n), out);
@@ -755,7 +792,7 @@ int apss_query_device(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, cons
   QueryStage qs;
   int rc = stage_queries(ix, nq, q_row_ptr, q_col, q_val, on_device, t_per_row, t, qs);
   if (rc) return rc;
-  QuerySet Q{qs.rows.rp.p, qs.rows.rc.p, qs.rows.mw.p, nq, qs.rows.nnz};
+  QuerySet Q{qs.rows.rp.p, qs.rows.rc.p, qs.rows.mw.p, nq, qs.rows.nnz, qs.rp_host.data()};
   int64_t cnt = 0;
   if ((rc = run_join(ix, Q, 0, t, t_per_row ? qs.qt.p : nullptr, &cnt))) return rc;
   return finish_device(ix, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count);
@@ -773,7 +810,7 @@ int apss_query(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, const int32
   QueryStage qs;
   int rc = stage_queries(ix, nq, q_row_ptr, q_col, q_val, on_device, t_per_row, t, qs);
   if (rc) return rc;
-  QuerySet Q{qs.rows.rp.p, qs.rows.rc.p, qs.rows.mw.p, nq, qs.rows.nnz};
+  QuerySet Q{qs.rows.rp.p, qs.rows.rc.p, qs.rows.mw.p, nq, qs.rows.nnz, qs.rp_host.data()};
   int64_t cnt = 0;
   if ((rc = run_join(ix, Q, 0, t, t_per_row ? qs.qt.p : nullptr, &cnt))) return rc;
   return finish_host(ix, cnt, ceil_log2((uint64_t)ix->n), out);

@@ -27,6 +27,7 @@ struct JoinArgs {
   int64_t nq;
   int32_t triangle;       // 1: self-join, query q only meets corpus rows y < q
   int64_t ntiles;
+  const int64_t* tstart;  // [ntiles+1] first query of each tile (tiles hold <= QT queries)
   // work items (corpus range of K blocks, query tile), queued per XCD
   const uint32_t* toff;   // [(nR+1) * m_tail] first entry of sparse list H + rt at or after range R
   int32_t m_tail;         // m - H
@@ -46,13 +47,15 @@ struct JoinArgs {
 
 // True when every device buffer the join kernel dereferences is present.
 inline bool join_args_complete(const JoinArgs& a) {
-  return a.rp && a.rc && a.rs && a.off && a.post && a.post4 && a.hoff && a.qrp && a.qrc && a.qmw && a.toff &&
+  return a.rp && a.rc && a.rs && a.off && a.post && a.post4 && a.hoff && a.qrp && a.qrc && a.qmw && a.toff && a.tstart &&
          a.qcum && a.qctr && a.wg_cur && a.out_key && a.out_sim && a.counters;
 }
 
 // Compiled tile variants of the join kernel.
 int join_num_variants();
 int join_variant_geometry(int variant, int* queries_per_tile, int* block_rows);
+// Components of one tile that the variant stages in LDS.
+int join_variant_staging(int variant);
 hipError_t launch_join(const JoinArgs& a, int variant, int grid, hipStream_t s);
 // Workgroups of a variant that fit on the device at once.
 int join_resident_groups(int variant);

@@ -163,8 +163,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       const int64_t R = (int64_t)x + 8 * (int64_t)lo_j;
       const int64_t tile = a.ntiles - 1 - (it - cum[lo_j]);
       const int64_t b_begin = R * a.K;
-  const int64_t q0 = tile * QT;
-  const int qn = (int)((a.nq - q0) < QT ? (a.nq - q0) : QT);
+  const int64_t q0 = a.tstart[tile];
+  const int qn = (int)(a.tstart[tile + 1] - q0);
 
   if (tid <= qn) sm.qoff[tid] = a.qrp[q0 + tid];
   if (tid < QT) {
@@ -460,15 +460,15 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         }
       }
       // long segments: wave w walks segments w, w + NW, ... in chunks of 64
-      // entries (one entry per lane) with all bookkeeping uniform; U chunks,
-      // possibly from different segments, are loaded before accumulating
+      // entries (one entry per lane) with all bookkeeping uniform.  Two
+      // batches of UL chunks alternate: the next batch's loads are issued
+      // before the current batch is accumulated, so loads stay in flight.
       {
         int si = wave, off = 0;
         uint32_t spos = 0, slenq = 0, sq = 0;
         int cur_si = -1;
-        while (si < nl) {
-          uint32_t cpos[UL], cq[UL];
-          int ccnt[UL], cab[UL];
+        // next UL chunks of this wave's segments (uniform values)
+        auto gather = [&](uint32_t (&cpos)[UL], uint32_t (&cq)[UL], int (&ccnt)[UL], int (&cab)[UL]) {
 #pragma unroll
           for (int u = 0; u < UL; ++u) {
             ccnt[u] = 0;
@@ -496,12 +496,16 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
               }
             }
           }
-          // one buffer load per chunk: scalar base, lane offset; lanes past
-          // the chunk read other entries (or zeros past the array) and are
-          // masked below
-          uint32_t p[UL];
+        };
+        // one buffer load per chunk: scalar base, lane offset; lanes past the
+        // chunk read other entries (or zeros past the array) and are masked
+        auto issue = [&](uint32_t (&p)[UL], const uint32_t (&cpos)[UL]) {
 #pragma unroll
-          for (int u = 0; u < UL; ++u) p[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, lane * 4, (int)(cpos[u] * 4u), 0);
+          for (int u = 0; u < UL; ++u)
+            p[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, lane * 4, (int)(cpos[u] * 4u), 0);
+        };
+        auto consume = [&](const uint32_t (&p)[UL], const uint32_t (&cq)[UL], const int (&ccnt)[UL],
+                           const int (&cab)[UL]) {
 #pragma unroll
           for (int u = 0; u < UL; ++u) {
             if (ccnt[u] > 0) {
@@ -509,6 +513,20 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
               if (lane < ccnt[u]) atomicAdd(&sm.acc[cab[u] + (int)(p[u] & (CB - 1))], packed_product(cq[u], p[u]));
             }
           }
+        };
+        uint32_t apos[UL], aq[UL], pa[UL], bpos[UL], bq[UL], pb[UL];
+        int acnt[UL], aab[UL], bcnt[UL], bab[UL];
+        gather(apos, aq, acnt, aab);
+        issue(pa, apos);
+        for (;;) {
+          if (acnt[0] <= 0) break;
+          gather(bpos, bq, bcnt, bab);
+          issue(pb, bpos);
+          consume(pa, aq, acnt, aab);
+          if (bcnt[0] <= 0) break;
+          gather(apos, aq, acnt, aab);
+          issue(pa, apos);
+          consume(pb, bq, bcnt, bab);
         }
       }
       __syncthreads();
@@ -741,11 +759,21 @@ hipError_t launch_unpack_pairs(const uint64_t* keys, const float* sim, int64_t c
 //  survivor queue, staged components, loads in flight for short / long
 //  segments, waves per SIMD)
 using V0 = Cfg<8, 2048, 512, 512, 1024, 1024, 8, 8, 2>;
-using V1 = Cfg<8, 1024, 512, 128, 512, 1024, 4, 8, 4>;
+using V1 = Cfg<8, 1024, 512, 128, 512, 1024, 4, 4, 4>;
 using V2 = Cfg<16, 1024, 512, 256, 1024, 1536, 8, 8, 2>;
 using V3 = Cfg<4, 2048, 256, 256, 512, 1024, 8, 8, 2>;
 
 int join_num_variants() { return 4; }
+
+int join_variant_staging(int v) {
+  switch (v) {
+    case 0: return V0::QB;
+    case 1: return V1::QB;
+    case 2: return V2::QB;
+    case 3: return V3::QB;
+    default: return 0;
+  }
+}
 
 int join_variant_geometry(int v, int* qt, int* cb) {
   switch (v) {
