@@ -5,14 +5,25 @@ generation, bounds, verification, rescoring, pair compaction, sort and
 unpack into device output buffers.  Inputs (the index) and outputs stay in
 HBM.  Prints one JSON line.
 
+After the join, the serving workload (unless --no-serve): a resident index
+of 2,000,000 vectors (m = 1,000,000, nnz/vector lognormal mean 100 in
+5..2000, Zipf s = 1.0) built at t = 0.5, and requests of 1..4096 queries
+(log-uniform) with per-request t uniform in [0.5, 0.95], arriving as a
+Poisson process.  The saturation rate is measured first with a closed-loop
+burst; open-loop runs at fractions of it give p50/p99 latency at stated
+queries/s.
+
 Workload (default): 1,000,000 vectors, 1,000,000 dimensions, nnz/vector
 lognormal mean 120 (5..5000), dimension popularity Zipf s = 1.0, lognormal
 weights normalised to unit L2 norm (float32), t = 0.7; seeded synthetic.
 """
 import argparse
 import json
+import math
 import os
+import queue
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -68,6 +79,160 @@ def cpu_baseline(V, t, budget_s: float):
     }
 
 
+def percentile(x, q):
+    x = sorted(x)
+    if not x:
+        return None
+    k = min(len(x) - 1, max(0, int(math.ceil(q / 100.0 * len(x))) - 1))
+    return x[k]
+
+
+class ServeDriver:
+    """Client side of the serving benchmark: submits prepared requests at
+    given arrival times (retrying while the server answers APSS_EBUSY) and
+    collects results on a second thread.  Latency of a request = time from
+    its arrival to its result being ready in the server (admission wait
+    included)."""
+
+    def __init__(self, apss, srv):
+        self.apss = apss
+        self.srv = srv
+
+    def run(self, reqs, arrivals):
+        q = queue.Queue()
+        out = []
+        errors = []
+
+        def poller():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                rid, k, wait_ms = item
+                try:
+                    i, j, s, info = self.srv.poll(rid)
+                except Exception as e:  # keep draining; reported below
+                    errors.append(e)
+                    continue
+                out.append((k, wait_ms + info["latency_ms"], info, len(i)))
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t0 = time.perf_counter()
+        busy = 0
+        for k, (Q, tq) in enumerate(reqs):
+            at = t0 + arrivals[k]
+            d = at - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            while True:
+                rid = self.srv.try_submit(Q, t_per_row=tq)
+                if rid is not None:
+                    break
+                busy += 1
+                time.sleep(0.0005)
+            q.put((rid, k, 1000.0 * (time.perf_counter() - at)))
+        q.put(None)
+        th.join()
+        elapsed = time.perf_counter() - t0
+        if errors:
+            raise errors[0]
+        return out, elapsed, busy
+
+
+def serve_bench(args):
+    import numpy as np
+    import torch
+
+    import paper_1402_3010_amd as apss
+    from synth.corpus import make_corpus, make_queries, spec_for
+
+    spec = spec_for("c5", n=args.serve_n)
+    t0 = time.perf_counter()
+    V = make_corpus(spec)
+    log("serve corpus c5: n=%d nnz=%d (%.1f s)" % (V.n, V.nnz, time.perf_counter() - t0))
+    rp = torch.from_numpy(V.row_ptr).cuda()
+    col = torch.from_numpy(V.col).cuda()
+    val = torch.from_numpy(V.val).cuda()
+    t_build = np.float32(0.5)
+    ix = apss.Index.build((V.n, V.m, rp, col, val), t_build)
+    torch.cuda.synchronize()
+    del rp, col, val
+    log("serve index built: %s" % ix.sizes())
+
+    rng = np.random.default_rng(2005)
+
+    def requests(pool, k):
+        out, pos = [], 0
+        for _ in range(k):
+            nq = int(min(4096, max(1, math.floor(math.exp(rng.uniform(0.0, math.log(4097.0)))))))
+            rows = (np.arange(pos, pos + nq) % pool.n)
+            pos = (pos + nq) % pool.n
+            t = np.full(nq, rng.uniform(0.5, 0.95), np.float32)
+            out.append((pool.take_rows(rows), t))
+        return out
+
+    pool = make_queries(V, 32768, spec, seed=2005)
+    pool_fresh = make_queries(V, 32768, spec, seed=3005, frac_copies=0.0)
+    srv = apss.Server(ix, slots=args.serve_slots, max_batch_queries=4096)
+    drv = ServeDriver(apss, srv)
+    # warm-up, then saturation: all requests arrive at once
+    drv.run(requests(pool, 8), [0.0] * 8)
+    burst = requests(pool, args.serve_requests)
+    res, el, busy = drv.run(burst, [0.0] * len(burst))
+    nq_burst = sum(Q.n for Q, _ in burst)
+    sat_rps = len(burst) / el
+    sat_qps = nq_burst / el
+    log("serve saturation: %d requests, %d queries in %.2f s: %.1f req/s, %.0f queries/s"
+        % (len(burst), nq_burst, el, sat_rps, sat_qps))
+    curve = []
+    for frac in args.serve_load:
+        rate = frac * sat_rps
+        n_req = max(40, int(rate * args.serve_seconds))
+        reqs = requests(pool, n_req)
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=n_req)).tolist()
+        st0 = srv.stats()
+        res, el, busy = drv.run(reqs, arr)
+        st1 = srv.stats()
+        lat = [r[1] for r in res]
+        nq = sum(Q.n for Q, _ in reqs)
+        point = {"load": frac, "rate_rps": rate, "requests": n_req, "queries": nq,
+                 "qps": nq / el, "rps": n_req / el, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                 "mean_batch_requests": float(np.mean([r[2]["batch_requests"] for r in res])),
+                 "batches": st1["batches"] - st0["batches"],
+                 "overlapped_batches": st1["overlapped_batches"] - st0["overlapped_batches"],
+                 "busy_retries": busy, "pairs": int(sum(r[3] for r in res))}
+        curve.append(point)
+        log("serve load %.2f: %.1f req/s offered, %.0f queries/s, p50 %.1f ms, p99 %.1f ms"
+            % (frac, rate, point["qps"], point["p50_ms"], point["p99_ms"]))
+    # the middle load once more on queries without corpus copies
+    frac = args.serve_load[len(args.serve_load) // 2]
+    rate = frac * sat_rps
+    n_req = max(40, int(rate * args.serve_seconds))
+    reqs = requests(pool_fresh, n_req)
+    arr = np.cumsum(rng.exponential(1.0 / rate, size=n_req)).tolist()
+    res, el, busy = drv.run(reqs, arr)
+    lat = [r[1] for r in res]
+    fresh = {"load": frac, "rate_rps": rate, "qps": sum(Q.n for Q, _ in reqs) / el,
+             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "pairs": int(sum(r[3] for r in res))}
+    st = srv.stats()
+    srv.close()
+    ix.close()
+    mid = curve[len(curve) // 2]
+    return {
+        "workload": "c5: resident index of %d vectors, m=%d, nnz/vector lognormal mean 100 (5..2000), Zipf s=1.0, "
+                    "t_build=0.5; requests of 1..4096 queries (log-uniform), query nnz lognormal mean 100, "
+                    "10%% perturbed corpus copies, per-request t ~ U[0.5, 0.95], Poisson arrivals" % (V.n, V.m),
+        "slots": args.serve_slots,
+        "qps": mid["qps"], "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"], "at_load": mid["load"],
+        "saturation_qps": sat_qps, "saturation_rps": sat_rps,
+        "curve": curve,
+        "no_copies": fresh,
+        "peak_running_batches": st["peak_running"], "overlapped_batches": st["overlapped_batches"],
+        "regrows": st["regrows"], "failed": st["failed"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +243,14 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="fewer rows (same distributions), for quick checks")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--serve-n", type=int, default=None, help="fewer corpus rows for the serving workload")
+    ap.add_argument("--serve-slots", type=int, default=2)
+    ap.add_argument("--serve-requests", type=int, default=120, help="requests in the saturation burst")
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="length of each open-loop run")
+    ap.add_argument("--serve-load", type=float, nargs="+", default=[0.3, 0.6, 0.9],
+                    help="offered load as fractions of the saturation request rate")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), to calibrate "
                          "the FETCH_SIZE / WRITE_SIZE counters against a known byte count")
@@ -105,6 +278,9 @@ def main():
 
     apss.load()
     torch.cuda.set_device(0)
+    if args.serve_only:
+        print(json.dumps({"serve": serve_bench(args)}), flush=True)
+        return
     t = np.float32(args.t if args.t is not None else CONFIGS[args.config]["t"][0])
     spec = spec_for(args.config, n=args.n)
     t0 = time.perf_counter()
@@ -179,10 +355,17 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "kernel": "k_join", "kernel_ms": kms, "algorithmic_bytes": alg_bytes},
     }
+    ix.close()
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(V, t, args.cpu_budget)
-    ix.close()
+    del V
+    if not args.no_serve:
+        sv = serve_bench(args)
+        out["serve"] = sv
+        out["serve_p50_ms"] = sv["p50_ms"]
+        out["serve_p99_ms"] = sv["p99_ms"]
+        out["serve_qps"] = sv["qps"]
     print(json.dumps(out), flush=True)
 
 

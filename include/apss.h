@@ -25,7 +25,9 @@
  *  - Inputs are borrowed for the duration of the call only.
  *  - All work is issued on the stream given in apss_opts (NULL = the
  *    default stream); calls return after that work has finished.
- *  - An apss_index is not thread-safe: one call at a time per index.
+ *  - An apss_index is not thread-safe: one call at a time per index.  While
+ *    a server (below) is attached to it, use the index only through that
+ *    server; the index must outlive the server.
  *  - Return value: APSS_OK or an error code below; apss_last_error() then
  *    holds a message for the calling thread.
  */
@@ -45,8 +47,8 @@ enum {
   APSS_ENOMEM = 3,   /* device or host allocation failed */
   APSS_EDEVICE = 4,  /* HIP runtime error */
   APSS_ERANGE = 5,   /* caller's output buffer too small; *count holds the size needed */
-  APSS_EBUSY = 6,    /* reserved for admission control */
-  APSS_PENDING = 100 /* reserved: work not finished yet (not an error) */
+  APSS_EBUSY = 6,    /* server admission refused: budget or queue full, retry later */
+  APSS_PENDING = 100 /* apss_poll: request not finished yet (not an error) */
 };
 
 typedef struct apss_index apss_index;
@@ -62,6 +64,9 @@ typedef struct {
                             rows per block); -1 = the library's default.  The environment
                             variable APSS_VARIANT overrides it. */
   int32_t head_dims;     /* densest dimensions that get per-block list offsets (0 = default) */
+  int32_t range_rows;    /* corpus rows per work item of the join (rounded down to a multiple of the
+                            variant's block rows; 0 = default 8192).  The environment variable
+                            APSS_RANGE_ROWS overrides it. */
   int32_t reserved[8];
 } apss_opts;
 
@@ -143,6 +148,105 @@ int apss_index_sizes(const apss_index* idx, int64_t* n, int64_t* m, int64_t* nnz
 
 const char* apss_strerror(int code);
 const char* apss_last_error(void);
+
+/* ---- Serving: continuous batching of query requests on a resident index ----
+ *
+ * A server answers external queries (apss_query semantics, Algorithm 2
+ * against the resident index) for requests that arrive at any time from any
+ * thread.  Each slot is a host thread with its own HIP stream and scratch;
+ * a free slot takes every queued request that fits one batch (FIFO, at most
+ * max_batch_queries queries), runs them as one query set with per-row
+ * thresholds and hands each request its own part of the result.  Batches of
+ * different slots run on the device at the same time.  A request's result
+ * does not depend on what it was batched with.
+ *
+ * Admission: a request reserves
+ *   40 * nnz + 32 * nq + 28 * pairs_per_query * nq
+ * bytes of the device memory budget (query staging, sort scratch and its
+ * candidate/pair buffers) from submit until it completes; submit returns
+ * APSS_EBUSY instead of queueing while the reservations would exceed
+ * memory_budget or max_pending requests are held.  A batch whose pairs
+ * outgrow their reservation still completes (its buffers grow; counted in
+ * apss_server_stats.regrows).
+ *
+ * All server entry points are thread-safe, except apss_server_destroy, which
+ * must not overlap any other call on the same server. */
+typedef struct apss_server apss_server;
+
+#define APSS_SERVER_MAX_SLOTS 8
+
+typedef struct {
+  int32_t struct_size;        /* sizeof(apss_server_opts) */
+  int32_t slots;              /* batches in flight at once, 1..APSS_SERVER_MAX_SLOTS (default 2) */
+  int64_t max_batch_queries;  /* queries merged into one batch, and the largest request (default 4096) */
+  int64_t memory_budget;      /* device bytes that admitted requests may reserve (default 4 GiB) */
+  int64_t pairs_per_query;    /* output pairs reserved per query (default 256) */
+  int64_t max_pending;        /* requests held (queued, running or not yet polled) at most (default 4096) */
+  int32_t reserved[8];
+} apss_server_opts;
+
+void apss_server_default_opts(apss_server_opts* opts);
+
+/* Start a server on idx (built with query_safe = 1).  The server borrows
+ * idx.  Errors: APSS_EINVAL (options, query_safe = 0), APSS_ENOMEM, APSS_EDEVICE. */
+int apss_server_create(apss_index* idx, const apss_server_opts* opts, apss_server** out);
+
+/* Queue a request of nq query rows (host CSR, copied before return; the
+ * CSR conventions above) with thresholds t_per_row[q] (host, may be NULL:
+ * t for every row).  *req_id identifies it for apss_poll.  nq = 0 is a
+ * request with an empty result.
+ * Errors: APSS_EINVAL (bad CSR, nq > max_batch_queries), APSS_ETHRESH (a
+ * threshold outside [t_build, 1]), APSS_EBUSY (not admitted now: retry),
+ * APSS_ENOMEM (the request alone needs more than memory_budget). */
+int apss_submit(apss_server* srv, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col, const float* q_val,
+                const float* t_per_row, float t, uint64_t* req_id);
+
+/* Timing of one completed request (host clock, milliseconds). */
+typedef struct {
+  double queue_ms;         /* submit -> its batch started */
+  double service_ms;       /* batch start -> result ready */
+  double latency_ms;       /* submit -> result ready */
+  int64_t batch;           /* sequence number of its batch */
+  int32_t batch_requests;  /* requests in that batch */
+  int32_t slot;            /* slot that ran it */
+} apss_request_info;
+
+/* Wait up to timeout_ms (0: do not wait, < 0: no limit) for request req_id.
+ * Returns APSS_PENDING if it has not finished; otherwise the request's own
+ * status, with its pairs in *out on APSS_OK (out->i = row within the
+ * request, out->j = corpus row, sorted; free with apss_pairs_free), and
+ * forgets the request.  info (may be NULL) receives its timing once done.
+ * Errors: APSS_EINVAL (unknown or already collected id), or the error that
+ * ended its batch (APSS_ENOMEM, APSS_EDEVICE). */
+int apss_poll(apss_server* srv, uint64_t req_id, int timeout_ms, apss_pairs* out, apss_request_info* info);
+
+/* paused = 1: slots start no new batch (running batches finish; submit
+ * still admits and queues); paused = 0: resume.  For draining a server. */
+int apss_server_pause(apss_server* srv, int paused);
+
+typedef struct {
+  int32_t slots;
+  int32_t running;              /* batches on the device now */
+  int64_t submitted;            /* requests admitted */
+  int64_t rejected_busy;        /* submits refused with APSS_EBUSY */
+  int64_t completed;            /* requests finished (including failed) */
+  int64_t failed;               /* requests finished with an error */
+  int64_t queued;               /* requests waiting for a slot now */
+  int64_t batches;              /* batches started */
+  int64_t queries;              /* query rows in started batches */
+  int64_t overlapped_batches;   /* batches started while another batch was running */
+  int64_t peak_running;         /* most batches running at once */
+  int64_t regrows;              /* batches rerun because their pairs outgrew the reservation */
+  int64_t reserved_bytes;       /* budget reserved now */
+  int64_t peak_reserved_bytes;  /* most budget reserved at once */
+  int64_t device_bytes[APSS_SERVER_MAX_SLOTS]; /* scratch each slot holds on the device */
+} apss_server_counters;
+
+int apss_server_stats(apss_server* srv, apss_server_counters* out);
+
+/* Stop the slots after their running batches; queued requests are dropped.
+ * Frees results not yet collected. */
+void apss_server_destroy(apss_server* srv);
 
 #ifdef __cplusplus
 }

@@ -39,7 +39,8 @@ class ApssError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("stream", ctypes.c_void_p), ("query_safe", ctypes.c_int32),
-                ("variant", ctypes.c_int32), ("head_dims", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("variant", ctypes.c_int32), ("head_dims", ctypes.c_int32), ("range_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class Pairs(ctypes.Structure):
@@ -51,6 +52,27 @@ class Stats(ctypes.Structure):
     _fields_ = [("posting_visits", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("bound_survivors", ctypes.c_int64), ("verified", ctypes.c_int64), ("band", ctypes.c_int64),
                 ("matches", ctypes.c_int64), ("ms_candidates", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+SERVER_MAX_SLOTS = 8
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("slots", ctypes.c_int32), ("max_batch_queries", ctypes.c_int64),
+                ("memory_budget", ctypes.c_int64), ("pairs_per_query", ctypes.c_int64),
+                ("max_pending", ctypes.c_int64), ("reserved", ctypes.c_int32 * 8)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("service_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("batch", ctypes.c_int64), ("batch_requests", ctypes.c_int32), ("slot", ctypes.c_int32)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("running", ctypes.c_int32)] + [
+        (k, ctypes.c_int64) for k in ("submitted", "rejected_busy", "completed", "failed", "queued", "batches",
+                                      "queries", "overlapped_batches", "peak_running", "regrows", "reserved_bytes",
+                                      "peak_reserved_bytes")] + [("device_bytes", ctypes.c_int64 * SERVER_MAX_SLOTS)]
 
 
 _LIB = None
@@ -99,13 +121,29 @@ def load(path: str = LIB_PATH):
     lib.apss_strerror.restype = ctypes.c_char_p
     lib.apss_last_error.argtypes = []
     lib.apss_last_error.restype = ctypes.c_char_p
+    lib.apss_server_default_opts.argtypes = [ctypes.POINTER(ServerOpts)]
+    lib.apss_server_default_opts.restype = None
+    lib.apss_server_create.argtypes = [P, ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]
+    lib.apss_server_create.restype = ctypes.c_int
+    lib.apss_submit.argtypes = [P, i64, P, P, P, P, f32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.apss_submit.restype = ctypes.c_int
+    lib.apss_poll.argtypes = [P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(Pairs), ctypes.POINTER(RequestInfo)]
+    lib.apss_poll.restype = ctypes.c_int
+    lib.apss_server_pause.argtypes = [P, ctypes.c_int]
+    lib.apss_server_pause.restype = ctypes.c_int
+    lib.apss_server_stats.argtypes = [P, ctypes.POINTER(ServerCounters)]
+    lib.apss_server_stats.restype = ctypes.c_int
+    lib.apss_server_destroy.argtypes = [P]
+    lib.apss_server_destroy.restype = None
     _LIB = lib
     return lib
 
 
 EXPORTED = ("apss_default_opts", "apss_build_index", "apss_index_free", "apss_join_device", "apss_join",
             "apss_query", "apss_query_device", "apss_pairs_free", "apss_last_stats", "apss_index_export",
-            "apss_index_sizes", "apss_strerror", "apss_last_error")
+            "apss_index_sizes", "apss_strerror", "apss_last_error", "apss_server_default_opts",
+            "apss_server_create", "apss_submit", "apss_poll", "apss_server_pause", "apss_server_stats",
+            "apss_server_destroy")
 
 
 def strerror(code: int) -> str:
@@ -149,13 +187,15 @@ def current_stream_handle() -> Optional[int]:
     return None
 
 
-def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, variant: int = -1) -> Opts:
+def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, variant: int = -1,
+                 range_rows: int = 0) -> Opts:
     o = Opts()
     load().apss_default_opts(ctypes.byref(o))
     o.stream = stream
     o.query_safe = 1 if query_safe else 0
     o.head_dims = head_dims
     o.variant = variant
+    o.range_rows = range_rows
     return o
 
 
@@ -269,7 +309,7 @@ class Index:
 
     @classmethod
     def build(cls, V, t_build: float, stream=None, query_safe: bool = True, head_dims: int = 0,
-              on_device: bool = False, variant: int = -1) -> "Index":
+              on_device: bool = False, variant: int = -1, range_rows: int = 0) -> "Index":
         """V: object with n, m, row_ptr, col, val (numpy), or a tuple (n, m, row_ptr, col, val) of tensors."""
         if isinstance(V, tuple):
             n, m, rp, col, val = V
@@ -282,7 +322,7 @@ class Index:
             val = torch.from_numpy(np.ascontiguousarray(val, np.float32)).cuda()
         if stream is None:
             stream = current_stream_handle()
-        h = build_index(n, m, rp, col, val, t_build, default_opts(stream, query_safe, head_dims, variant))
+        h = build_index(n, m, rp, col, val, t_build, default_opts(stream, query_safe, head_dims, variant, range_rows))
         return cls(h, int(n), int(m))
 
     def join(self, t: float):
@@ -310,6 +350,106 @@ class Index:
         if self.handle:
             index_free(self.handle)
             self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- serving ----
+
+def server_default_opts(**kw) -> ServerOpts:
+    o = ServerOpts()
+    load().apss_server_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def server_create(index_handle: int, opts: Optional[ServerOpts] = None) -> int:
+    h = ctypes.c_void_p()
+    o = opts if opts is not None else server_default_opts()
+    _check(load().apss_server_create(index_handle, ctypes.byref(o), ctypes.byref(h)))
+    return h.value
+
+
+def submit(server_handle: int, nq: int, q_row_ptr, q_col, q_val, t: float = 0.0, t_per_row=None) -> int:
+    """apss_submit with host arrays; returns the request id (raises ApssError, code APSS_EBUSY when not admitted)."""
+    rp = np.ascontiguousarray(q_row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(q_col, dtype=np.int32)
+    v = np.ascontiguousarray(q_val, dtype=np.float32)
+    tq = None if t_per_row is None else np.ascontiguousarray(t_per_row, dtype=np.float32)
+    rid = ctypes.c_uint64()
+    _check(load().apss_submit(server_handle, int(nq), rp.ctypes.data, c.ctypes.data, v.ctypes.data,
+                              None if tq is None else tq.ctypes.data, float(t), ctypes.byref(rid)))
+    return rid.value
+
+
+def poll(server_handle: int, req_id: int, timeout_ms: int = -1):
+    """apss_poll: None while pending, else (i, j, sim, info dict)."""
+    p = Pairs()
+    info = RequestInfo()
+    rc = load().apss_poll(server_handle, ctypes.c_uint64(req_id), int(timeout_ms), ctypes.byref(p),
+                          ctypes.byref(info))
+    if rc == APSS_PENDING:
+        return None
+    _check(rc)
+    i, j, s = _take_pairs(p)
+    return i, j, s, {k: getattr(info, k) for k, _ in RequestInfo._fields_}
+
+
+def server_stats(server_handle: int) -> dict:
+    c = ServerCounters()
+    _check(load().apss_server_stats(server_handle, ctypes.byref(c)))
+    d = {k: getattr(c, k) for k, _ in ServerCounters._fields_ if k != "device_bytes"}
+    d["device_bytes"] = list(c.device_bytes)[:c.slots]
+    return d
+
+
+def server_destroy(server_handle: int):
+    load().apss_server_destroy(server_handle)
+
+
+class Server:
+    """Owning wrapper of an apss_server attached to an Index (which must stay open)."""
+
+    def __init__(self, index: Index, **opts):
+        self.index = index
+        self.handle = server_create(index.handle, server_default_opts(**opts))
+
+    def submit(self, Q, t: float = 0.0, t_per_row=None) -> int:
+        return submit(self.handle, Q.n, Q.row_ptr, Q.col, Q.val, t, t_per_row)
+
+    def try_submit(self, Q, t: float = 0.0, t_per_row=None) -> Optional[int]:
+        """Like submit, but None when the server refuses with APSS_EBUSY."""
+        try:
+            return self.submit(Q, t, t_per_row)
+        except ApssError as e:
+            if e.code == APSS_EBUSY:
+                return None
+            raise
+
+    def poll(self, req_id: int, timeout_ms: int = -1):
+        return poll(self.handle, req_id, timeout_ms)
+
+    def pause(self, paused: bool = True):
+        _check(load().apss_server_pause(self.handle, 1 if paused else 0))
+
+    def stats(self) -> dict:
+        return server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            server_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
     def __del__(self):
         try:

@@ -15,6 +15,7 @@
 #include "apss_internal.h"
 #include "index_build.h"
 #include "join.h"
+#include "lib.h"
 
 namespace apss {
 
@@ -32,40 +33,6 @@ void set_error(const char* fmt, ...) {
   last_error() = buf;
 }
 
-namespace {
-
-// Owned device allocation.
-template <typename T>
-struct DBuf {
-  T* p = nullptr;
-  int64_t n = 0;
-  DBuf() = default;
-  DBuf(const DBuf&) = delete;
-  DBuf& operator=(const DBuf&) = delete;
-  ~DBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
-  }
-  hipError_t alloc(int64_t count) {
-    release();
-    if (count <= 0) count = 1;
-    hipError_t e = hipMalloc((void**)&p, sizeof(T) * (size_t)count);
-    if (e != hipSuccess) {
-      p = nullptr;
-      return e;
-    }
-    n = count;
-    return hipSuccess;
-  }
-  // grow without preserving contents
-  hipError_t reserve(int64_t count) {
-    if (count <= n && p) return hipSuccess;
-    return alloc(count);
-  }
-};
-
 int dev_err(hipError_t e, const char* what) {
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
     set_error("%s: out of device memory", what);
@@ -76,26 +43,7 @@ int dev_err(hipError_t e, const char* what) {
   return APSS_EDEVICE;
 }
 
-#define CHK(expr, what)                         \
-  do {                                          \
-    hipError_t e__ = (expr);                    \
-    if (e__ != hipSuccess) return dev_err(e__, what); \
-  } while (0)
-
-// Rank-space rows of a query set (the corpus itself for the self-join).
-struct RankRows {
-  int64_t n = 0, nnz = 0;
-  DBuf<int64_t> rp;
-  DBuf<RComp> rc;
-  DBuf<float> mw;
-};
-
-// Sort scratch sized for the largest sort done so far.
-struct SortScratch {
-  DBuf<uint64_t> k1, k2, v64a, v64b;
-  DBuf<uint32_t> v32a, v32b;
-  DBuf<int64_t> hist, scan;
-};
+namespace {
 
 const char* err_bits_text(uint32_t e) {
   if (e & ERR_ROWPTR) return "row_ptr must start at 0, be non-decreasing and end at nnz";
@@ -109,52 +57,18 @@ const char* err_bits_text(uint32_t e) {
 }  // namespace
 }  // namespace apss
 
+
 using namespace apss;
 
-struct apss_index {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  apss_opts opts;
-  int64_t n = 0, m = 0, nnz = 0, P = 0;
-  float t_build = 0.0f;
-  int32_t H = 0;
-  RankRows rows;          // corpus rows in rank space (densest dimension first)
-  DBuf<RowStat> rs;
-  DBuf<int32_t> rank, inv;
-  DBuf<float> mw_r;       // maxweight by rank
-  DBuf<int64_t> off;
-  DBuf<Post> post;
-  DBuf<uint32_t> post4;   // packed copy of post for streaming
-  // per-block list offsets for each block width in use (index 0: 1024 rows, 1: 2048 rows)
-  DBuf<uint32_t> hoff[2];
-  int64_t hoff_nb[2] = {0, 0};
-  int variant = 0;
-  // range offsets of the sparse lists for one range width (rows)
-  DBuf<uint32_t> toff;
-  int64_t toff_rows = 0, toff_nR = 0;
-  std::vector<int64_t> rp_host;  // host copy of the corpus row offsets
-  // join workspace
-  DBuf<int64_t> tstart;
-  DBuf<uint32_t> wg_cur;
-  DBuf<int64_t> qcum;
-  DBuf<unsigned int> qctr;
-  DBuf<unsigned long long> scalar;
-  int grid[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  DBuf<uint64_t> raw_key;
-  DBuf<float> raw_sim;
-  DBuf<unsigned long long> counters;
-  SortScratch ss;
-  apss_stats last;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-};
+#define CHK APSS_CHK
 
 namespace {
 
 // Sort (row, rank) keys with float payload into rank-space rows; checks for duplicates.
-int sort_rows(apss_index* ix, uint64_t* keys, uint32_t* vals, int64_t nnz, int key_bits, int rbits, RComp* rc_out,
+int sort_rows(Workspace& ws, uint64_t* keys, uint32_t* vals, int64_t nnz, int key_bits, int rbits, RComp* rc_out,
               uint32_t* err_dev) {
-  hipStream_t s = ix->stream;
-  SortScratch& ss = ix->ss;
+  hipStream_t s = ws.stream;
+  SortScratch& ss = ws.ss;
   CHK(ss.k2.reserve(nnz), "sort scratch");
   CHK(ss.v32b.reserve(nnz), "sort scratch");
   CHK(ss.hist.reserve(radix_hist_elems(nnz)), "sort scratch");
@@ -164,17 +78,26 @@ int sort_rows(apss_index* ix, uint64_t* keys, uint32_t* vals, int64_t nnz, int k
   return APSS_OK;
 }
 
-int check_err(apss_index* ix, uint32_t* err_dev, unsigned long long* bad_dev, const char* what) {
+int check_err(hipStream_t s, uint32_t* err_dev, unsigned long long* bad_dev, const char* what) {
   uint32_t err = 0;
   unsigned long long bad = ~0ull;
-  CHK(hipMemcpyAsync(&err, err_dev, sizeof(err), hipMemcpyDeviceToHost, ix->stream), what);
-  if (bad_dev) CHK(hipMemcpyAsync(&bad, bad_dev, sizeof(bad), hipMemcpyDeviceToHost, ix->stream), what);
-  CHK(hipStreamSynchronize(ix->stream), what);
+  CHK(hipMemcpyAsync(&err, err_dev, sizeof(err), hipMemcpyDeviceToHost, s), what);
+  if (bad_dev) CHK(hipMemcpyAsync(&bad, bad_dev, sizeof(bad), hipMemcpyDeviceToHost, s), what);
+  CHK(hipStreamSynchronize(s), what);
   if (err) {
     if (bad != ~0ull) set_error("%s: %s (row %llu)", what, err_bits_text(err), bad);
     else set_error("%s: %s", what, err_bits_text(err));
     return APSS_EINVAL;
   }
+  return APSS_OK;
+}
+
+// Cleared error flag and first-bad-row slot of a workspace.
+int reset_err(Workspace& ws) {
+  CHK(ws.err.reserve(1), "alloc");
+  CHK(ws.bad.reserve(1), "alloc");
+  CHK(fill_u32(ws.err.p, 0u, 1, ws.stream), "fill");
+  CHK(fill_u64((uint64_t*)ws.bad.p, ~0ull, 1, ws.stream), "fill");
   return APSS_OK;
 }
 
@@ -188,9 +111,8 @@ struct CsrDev {
   const float* pval = nullptr;
 };
 
-int stage_csr(apss_index* ix, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val, int on_device,
+int stage_csr(hipStream_t s, int64_t n, const int64_t* row_ptr, const int32_t* col, const float* val, int on_device,
               int64_t* nnz_out, CsrDev& d) {
-  hipStream_t s = ix->stream;
   int64_t nnz = 0;
   if (on_device) {
     CHK(hipMemcpyAsync(&nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read nnz");
@@ -231,41 +153,23 @@ int stage_csr(apss_index* ix, int64_t n, const int64_t* row_ptr, const int32_t* 
 
 int hoff_slot(int cb) { return cb == 1024 ? 0 : 1; }
 
-// Per-(block, rank) list offsets for the block width of a tile variant.
-int ensure_hoff(apss_index* ix, int variant) {
-  int qt = 0, cb = 0;
-  if (join_variant_geometry(variant, &qt, &cb)) {
-    set_error("unknown join variant %d", variant);
-    return APSS_EINVAL;
-  }
-  const int slot = hoff_slot(cb);
-  if (ix->hoff[slot].p) return APSS_OK;
-  const int64_t nb = (ix->n + cb - 1) / cb;
-  CHK(ix->hoff[slot].alloc((nb + 1) * (int64_t)ix->H), "alloc block offsets");
-  CHK(launch_block_offsets(ix->off.p, ix->post.p, ix->H, nb, cb, ix->hoff[slot].p, ix->stream), "block offsets");
-  ix->hoff_nb[slot] = nb;
-  return APSS_OK;
-}
-
 int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const float* val, int on_device) {
-  hipStream_t s = ix->stream;
+  Workspace& ws = ix->ws;
+  hipStream_t s = ws.stream;
   const int64_t n = ix->n, m = ix->m;
   CsrDev in;
   int64_t nnz = 0;
-  int rc = stage_csr(ix, n, row_ptr, col, val, on_device, &nnz, in);
+  int rc = stage_csr(s, n, row_ptr, col, val, on_device, &nnz, in);
   if (rc) return rc;
   ix->nnz = nnz;
 
-  DBuf<uint32_t> err;
-  DBuf<unsigned long long> bad;
-  CHK(err.alloc(1), "alloc");
-  CHK(bad.alloc(1), "alloc");
-  CHK(fill_u32(err.p, 0u, 1, s), "fill");
-  CHK(fill_u64((uint64_t*)bad.p, ~0ull, 1, s), "fill");
-  CHK(launch_check_rowptr(in.prp, n, nnz, err.p, bad.p, s), "check row_ptr");
-  if ((rc = check_err(ix, err.p, bad.p, "build_index"))) return rc;
-  CHK(launch_validate_rows(in.prp, in.pcol, in.pval, n, m, 1e-5, err.p, bad.p, s), "validate");
-  if ((rc = check_err(ix, err.p, bad.p, "build_index"))) return rc;
+  if ((rc = reset_err(ws))) return rc;
+  uint32_t* err = ws.err.p;
+  unsigned long long* bad = ws.bad.p;
+  CHK(launch_check_rowptr(in.prp, n, nnz, err, bad, s), "check row_ptr");
+  if ((rc = check_err(s, err, bad, "build_index"))) return rc;
+  CHK(launch_validate_rows(in.prp, in.pcol, in.pval, n, m, 1e-5, err, bad, s), "validate");
+  if ((rc = check_err(s, err, bad, "build_index"))) return rc;
 
   // density order and maxweight_d(V)
   DBuf<uint32_t> cnt, mwbits, cnt_r;
@@ -277,7 +181,7 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   CHK(launch_count_dims(in.pcol, in.pval, nnz, cnt.p, mwbits.p, s), "count dims");
   const int dbits = ceil_log2((uint64_t)m);
   const int cbits = ceil_log2((uint64_t)n + 1);
-  SortScratch& ss = ix->ss;
+  SortScratch& ss = ws.ss;
   const int64_t big = std::max<int64_t>(nnz, m);
   CHK(ss.k1.reserve(big), "alloc sort");
   CHK(ss.v64a.reserve(m), "alloc sort");
@@ -302,11 +206,11 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   ix->rows.nnz = nnz;
   CHK(ix->rows.rp.alloc(n + 1), "alloc");
   CHK(hipMemcpyAsync(ix->rows.rp.p, in.prp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s), "copy");
-  ix->rp_host.resize((size_t)n + 1);
-  CHK(hipMemcpyAsync(ix->rp_host.data(), in.prp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s), "copy");
+  ix->rows.rp_host.resize((size_t)n + 1);
+  CHK(hipMemcpyAsync(ix->rows.rp_host.data(), in.prp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s), "copy");
   CHK(ix->rows.rc.alloc(nnz), "alloc");
-  if ((rc = sort_rows(ix, ss.k1.p, ss.v32a.p, nnz, nbits + rbits, rbits, ix->rows.rc.p, err.p))) return rc;
-  if ((rc = check_err(ix, err.p, nullptr, "build_index"))) return rc;
+  if ((rc = sort_rows(ws, ss.k1.p, ss.v32a.p, nnz, nbits + rbits, rbits, ix->rows.rc.p, err))) return rc;
+  if ((rc = check_err(s, err, nullptr, "build_index"))) return rc;
 
   // cutoff of the unindexed part
   CHK(ix->rs.alloc(n), "alloc");
@@ -354,7 +258,7 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   int32_t H = ix->opts.head_dims > 0 ? ix->opts.head_dims : 32768;
   if (H > m) H = (int32_t)m;
   ix->H = H;
-  if ((rc = ensure_hoff(ix, ix->variant))) return rc;
+  if ((rc = prepare(ix, s, ix->variant, ix->range_rows))) return rc;
   CHK(hipStreamSynchronize(s), "build_index");
   // sort scratch is re-grown on demand by the joins
   ss.k1.release();
@@ -365,14 +269,6 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   ss.v32b.release();
   return APSS_OK;
 }
-
-struct QuerySet {
-  const int64_t* rp;       // device
-  const RComp* rc;
-  const float* mw;
-  int64_t n, nnz;
-  const int64_t* rp_host;  // host copy of rp
-};
 
 // Query tiles: consecutive queries, at most QT of them and, unless a single
 // query is larger, at most QB components, so that a tile fits the LDS staging.
@@ -400,14 +296,57 @@ Tiles make_tiles(const int64_t* rp, int64_t n, int QT, int QB) {
   return T;
 }
 
-// Run the join kernels; raw (unsorted) pairs in ix->raw_key / raw_sim, count in *count.
-int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const float* qt_dev, int64_t* count) {
-  hipStream_t s = ix->stream;
-  memset(&ix->last, 0, sizeof(ix->last));
+}  // namespace
+
+namespace apss {
+
+int64_t default_range_rows(int variant) {
+  int qt = 0, cb = 1024;
+  (void)join_variant_geometry(variant, &qt, &cb);
+  return (int64_t)std::max(1, 8192 / cb) * cb;
+}
+
+int prepare(apss_index* ix, hipStream_t s, int variant, int64_t range_rows) {
+  int qt = 0, cb = 0;
+  if (join_variant_geometry(variant, &qt, &cb)) {
+    set_error("unknown join variant %d", variant);
+    return APSS_EINVAL;
+  }
+  const int64_t K = std::max<int64_t>(1, range_rows / cb);
+  range_rows = K * cb;
+  std::lock_guard<std::mutex> lock(ix->prep_mu);
+  bool built = false;
+  const int slot = hoff_slot(cb);
+  if (!ix->hoff[slot].p) {
+    const int64_t nb = (ix->n + cb - 1) / cb;
+    CHK(ix->hoff[slot].alloc((nb + 1) * (int64_t)ix->H), "alloc block offsets");
+    CHK(launch_block_offsets(ix->off.p, ix->post.p, ix->H, nb, cb, ix->hoff[slot].p, s), "block offsets");
+    ix->hoff_nb[slot] = nb;
+    built = true;
+  }
+  if (!ix->toff.p || ix->toff_rows != range_rows) {
+    const int64_t nb = (ix->n + cb - 1) / cb;
+    const int64_t nR = (nb + K - 1) / K;
+    CHK(ix->toff.alloc((nR + 1) * std::max<int64_t>(ix->m - ix->H, 1)), "alloc range offsets");
+    CHK(launch_range_offsets(ix->off.p, ix->post.p, ix->H, ix->m, nR, range_rows, ix->toff.p, s), "range offsets");
+    ix->toff_rows = range_rows;
+    ix->toff_nR = nR;
+    built = true;
+  }
+  if (!ix->grid[variant]) ix->grid[variant] = join_resident_groups(variant);
+  // other streams read the tables as soon as the lock is released
+  if (built) CHK(hipStreamSynchronize(s), "prepare");
+  return APSS_OK;
+}
+
+int run_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, float t, const float* qt_dev,
+             int64_t cap_hint, int64_t* count) {
+  hipStream_t s = ws.stream;
+  memset(&ws.last, 0, sizeof(ws.last));
   *count = 0;
   for (int e = 0; e < 4; ++e)
-    if (!ix->ev[e]) CHK(hipEventCreate(&ix->ev[e]), "event");
-  CHK(hipEventRecord(ix->ev[0], s), "event");
+    if (!ws.ev[e]) CHK(hipEventCreateWithFlags(&ws.ev[e], hipEventDefault), "event");
+  CHK(hipEventRecord(ws.ev[0], s), "event");
   if (Q.n == 0 || ix->n == 0) return APSS_OK;
   const int variant = ix->variant;
   int QT = 0, CB = 0;
@@ -415,28 +354,18 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     set_error("unknown join variant %d", variant);
     return APSS_EINVAL;
   }
-  int rc0 = ensure_hoff(ix, variant);
+  int rc0 = prepare(ix, s, variant, ix->range_rows);
   if (rc0) return rc0;
   const int slot = hoff_slot(CB);
   const int64_t nb = ix->hoff_nb[slot];
   // work items: ranges of K blocks x query tiles
-  int K = std::max(1, 8192 / CB);
-  if (const char* ev = getenv("APSS_RANGE_ROWS")) {
-    const int rr = atoi(ev);
-    if (rr >= CB) K = rr / CB;
-  }
-  const int64_t nR = (nb + K - 1) / K;
-  const int64_t range_rows = (int64_t)K * CB;
-  if (!ix->toff.p || ix->toff_rows != range_rows) {
-    CHK(ix->toff.alloc((nR + 1) * std::max<int64_t>(ix->m - ix->H, 1)), "alloc range offsets");
-    CHK(launch_range_offsets(ix->off.p, ix->post.p, ix->H, ix->m, nR, range_rows, ix->toff.p, s), "range offsets");
-    ix->toff_rows = range_rows;
-    ix->toff_nR = nR;
-  }
+  const int64_t range_rows = ix->toff_rows;
+  const int K = (int)(range_rows / CB);
+  const int64_t nR = ix->toff_nR;
   const Tiles tiles = make_tiles(Q.rp_host, Q.n, QT, join_variant_staging(variant));
   const int64_t ntiles = (int64_t)tiles.start.size() - 1;
-  CHK(ix->tstart.reserve(ntiles + 1), "alloc tiles");
-  CHK(hipMemcpyAsync(ix->tstart.p, tiles.start.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, s),
+  CHK(ws.tstart.reserve(ntiles + 1), "alloc tiles");
+  CHK(hipMemcpyAsync(ws.tstart.p, tiles.start.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, s),
       "tiles");
   const int64_t nrx = (nR + 7) / 8;
   std::vector<int64_t> cum((size_t)(8 * (nrx + 1)), 0);
@@ -455,26 +384,24 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
       }
     }
   }
-  CHK(ix->qcum.reserve((int64_t)cum.size()), "alloc queues");
-  CHK(hipMemcpyAsync(ix->qcum.p, cum.data(), sizeof(int64_t) * cum.size(), hipMemcpyHostToDevice, s), "queues");
-  CHK(ix->qctr.reserve(8), "alloc queues");
-  CHK(ix->counters.reserve(C_NUM), "alloc counters");
-  if (!ix->grid[variant]) ix->grid[variant] = join_resident_groups(variant);
+  CHK(ws.qcum.reserve((int64_t)cum.size()), "alloc queues");
+  CHK(hipMemcpyAsync(ws.qcum.p, cum.data(), sizeof(int64_t) * cum.size(), hipMemcpyHostToDevice, s), "queues");
+  CHK(ws.qctr.reserve(8), "alloc queues");
+  CHK(ws.counters.reserve(C_NUM), "alloc counters");
   const int G = ix->grid[variant];
   // per-workgroup cursor space for tiles too large to stage in LDS
   const int64_t wg_stride = 2 * std::max<int64_t>(tiles.max_nnz, 1);
-  CHK(ix->wg_cur.reserve((int64_t)G * wg_stride), "alloc cursors");
-  if (!ix->raw_key.p) {
-    const int64_t cap0 = std::max<int64_t>(1 << 20, 16 * std::max(ix->n, Q.n));
-    CHK(ix->raw_key.alloc(cap0), "alloc pairs");
-    CHK(ix->raw_sim.alloc(cap0), "alloc pairs");
+  CHK(ws.wg_cur.reserve((int64_t)G * wg_stride), "alloc cursors");
+  if (ws.raw_key.n < cap_hint || !ws.raw_key.p) {
+    const int64_t cap0 = std::max<int64_t>(cap_hint, 1 << 16);
+    CHK(ws.raw_key.alloc(cap0), "alloc pairs");
+    CHK(ws.raw_sim.alloc(cap0), "alloc pairs");
   }
-  const int bj = ceil_log2((uint64_t)(triangle ? ix->n : ix->n));
+  const int bj = ceil_log2((uint64_t)ix->n);
   const int bi = ceil_log2((uint64_t)(triangle ? ix->n : Q.n));
   for (int attempt = 0; attempt < 2; ++attempt) {
-    CHK(hipEventRecord(ix->ev[0], s), "event");
-    CHK(fill_u64((uint64_t*)ix->counters.p, 0ull, C_NUM, s), "fill");
-    CHK(fill_u32(ix->qctr.p, 0u, 8, s), "fill");
+    CHK(fill_u64((uint64_t*)ws.counters.p, 0ull, C_NUM, s), "fill");
+    CHK(fill_u32(ws.qctr.p, 0u, 8, s), "fill");
     JoinArgs a;
     a.rp = ix->rows.rp.p;
     a.rc = ix->rows.rc.p;
@@ -495,53 +422,54 @@ int run_join(apss_index* ix, const QuerySet& Q, int triangle, float t, const flo
     a.nq = Q.n;
     a.triangle = triangle;
     a.ntiles = ntiles;
-    a.tstart = ix->tstart.p;
+    a.tstart = ws.tstart.p;
     a.toff = ix->toff.p;
     a.m_tail = (int32_t)(ix->m - ix->H);
     a.K = K;
     a.nrx = nrx;
-    a.qcum = ix->qcum.p;
-    a.qctr = ix->qctr.p;
-    a.wg_cur = ix->wg_cur.p;
+    a.qcum = ws.qcum.p;
+    a.qctr = ws.qctr.p;
+    a.wg_cur = ws.wg_cur.p;
     a.wg_cur_stride = wg_stride;
-    a.out_key = ix->raw_key.p;
-    a.out_sim = ix->raw_sim.p;
-    a.cap = ix->raw_key.n;
+    a.out_key = ws.raw_key.p;
+    a.out_sim = ws.raw_sim.p;
+    a.cap = ws.raw_key.n;
     a.bj = bj;
-    a.counters = ix->counters.p;
-    CHK(hipEventRecord(ix->ev[1], s), "event");
+    a.counters = ws.counters.p;
+    CHK(hipEventRecord(ws.ev[1], s), "event");
     if (!join_args_complete(a)) {
       set_error("internal: join launched with a missing device buffer");
       return APSS_EDEVICE;
     }
     CHK(launch_join(a, variant, G, s), "join kernel");
-    CHK(hipEventRecord(ix->ev[2], s), "event");
+    CHK(hipEventRecord(ws.ev[2], s), "event");
     unsigned long long c[C_NUM];
-    CHK(hipMemcpyAsync(c, ix->counters.p, sizeof(c), hipMemcpyDeviceToHost, s), "read counters");
+    CHK(hipMemcpyAsync(c, ws.counters.p, sizeof(c), hipMemcpyDeviceToHost, s), "read counters");
     CHK(hipStreamSynchronize(s), "join");
     const int64_t matches = (int64_t)c[C_MATCHES];
-    if (matches > ix->raw_key.n) {
+    if (matches > ws.raw_key.n) {
       const int64_t cap = matches + matches / 8 + 1024;
-      CHK(ix->raw_key.alloc(cap), "alloc pairs");
-      CHK(ix->raw_sim.alloc(cap), "alloc pairs");
+      CHK(ws.raw_key.alloc(cap), "alloc pairs");
+      CHK(ws.raw_sim.alloc(cap), "alloc pairs");
+      ++ws.regrows;
       continue;  // rerun with room for every pair
     }
-    ix->last.posting_visits = (int64_t)(c[C_VISITS] + c[C_TAILVISITS]);
-    ix->last.candidates = (int64_t)c[C_CANDIDATES];
-    ix->last.bound_survivors = (int64_t)c[C_SURVIVORS];
-    ix->last.verified = (int64_t)c[C_VERIFIED];
-    ix->last.band = (int64_t)c[C_BAND];
-    ix->last.matches = matches;
+    ws.last.posting_visits = (int64_t)(c[C_VISITS] + c[C_TAILVISITS]);
+    ws.last.candidates = (int64_t)c[C_CANDIDATES];
+    ws.last.bound_survivors = (int64_t)c[C_SURVIVORS];
+    ws.last.verified = (int64_t)c[C_VERIFIED];
+    ws.last.band = (int64_t)c[C_BAND];
+    ws.last.matches = matches;
     float ms = 0.0f;
-    CHK(hipEventElapsedTime(&ms, ix->ev[1], ix->ev[2]), "event");
-    ix->last.ms_candidates = ms;
+    CHK(hipEventElapsedTime(&ms, ws.ev[1], ws.ev[2]), "event");
+    ws.last.ms_candidates = ms;
     // sort by key
-    SortScratch& ss = ix->ss;
+    SortScratch& ss = ws.ss;
     CHK(ss.k2.reserve(matches), "alloc sort");
     CHK(ss.v32b.reserve(matches), "alloc sort");
     CHK(ss.hist.reserve(radix_hist_elems(matches)), "alloc sort");
     CHK(ss.scan.reserve(radix_scan_tmp_elems(matches)), "alloc sort");
-    CHK(radix_sort_u64_u32(ix->raw_key.p, (uint32_t*)ix->raw_sim.p, ss.k2.p, ss.v32b.p, matches, bi + bj, ss.hist.p,
+    CHK(radix_sort_u64_u32(ws.raw_key.p, (uint32_t*)ws.raw_sim.p, ss.k2.p, ss.v32b.p, matches, bi + bj, ss.hist.p,
                            ss.scan.p, s),
         "pair sort");
     *count = matches;
@@ -563,33 +491,36 @@ int check_t(const apss_index* ix, float t) {
   return APSS_OK;
 }
 
-int finish_device(apss_index* ix, int64_t cnt, int bj, uint32_t* out_i, uint32_t* out_j, float* out_sim,
+int finish_device(Workspace& ws, int64_t cnt, int bj, uint32_t* out_i, uint32_t* out_j, float* out_sim,
                   int64_t capacity, int64_t* count) {
   *count = cnt;
   if (cnt > capacity) {
     set_error("output capacity %lld too small for %lld pairs", (long long)capacity, (long long)cnt);
     return APSS_ERANGE;
   }
-  CHK(launch_unpack_pairs(ix->raw_key.p, ix->raw_sim.p, cnt, bj, out_i, out_j, out_sim, ix->stream), "unpack");
-  CHK(hipEventRecord(ix->ev[3], ix->stream), "event");
-  CHK(hipStreamSynchronize(ix->stream), "unpack");
+  CHK(launch_unpack_pairs(ws.raw_key.p, ws.raw_sim.p, cnt, bj, out_i, out_j, out_sim, ws.stream), "unpack");
+  CHK(hipEventRecord(ws.ev[3], ws.stream), "event");
+  CHK(hipStreamSynchronize(ws.stream), "unpack");
   float ms = 0.0f;
-  CHK(hipEventElapsedTime(&ms, ix->ev[0], ix->ev[3]), "event");
-  ix->last.ms_total = ms;
+  CHK(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[3]), "event");
+  ws.last.ms_total = ms;
   return APSS_OK;
 }
 
-int finish_host(apss_index* ix, int64_t cnt, int bj, apss_pairs* out) {
+int finish_host(Workspace& ws, int64_t cnt, int bj, apss_pairs* out) {
   out->count = 0;
   out->i = out->j = nullptr;
   out->sim = nullptr;
-  DBuf<uint32_t> di, dj;
-  DBuf<float> ds;
-  CHK(di.alloc(cnt), "alloc");
-  CHK(dj.alloc(cnt), "alloc");
-  CHK(ds.alloc(cnt), "alloc");
+  // the sort's second key buffer is free once the pairs are sorted: unpack there
+  SortScratch& ss = ws.ss;
+  CHK(ss.k2.reserve(cnt), "alloc");
+  CHK(ss.v32b.reserve(cnt), "alloc");
+  CHK(ss.v32a.reserve(cnt), "alloc");
+  uint32_t* di = (uint32_t*)ss.k2.p;
+  uint32_t* dj = ss.v32a.p;
+  float* ds = (float*)ss.v32b.p;
   int64_t c2 = 0;
-  int rc = finish_device(ix, cnt, bj, di.p, dj.p, ds.p, cnt, &c2);
+  int rc = finish_device(ws, cnt, bj, di, dj, ds, cnt, &c2);
   if (rc) return rc;
   const size_t nb = (size_t)(cnt > 0 ? cnt : 1);
   out->i = (uint32_t*)malloc(nb * sizeof(uint32_t));
@@ -605,25 +536,18 @@ int finish_host(apss_index* ix, int64_t cnt, int bj, apss_pairs* out) {
     return APSS_ENOMEM;
   }
   if (cnt) {
-    CHK(hipMemcpyAsync(out->i, di.p, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost, ix->stream), "copy out");
-    CHK(hipMemcpyAsync(out->j, dj.p, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost, ix->stream), "copy out");
-    CHK(hipMemcpyAsync(out->sim, ds.p, sizeof(float) * cnt, hipMemcpyDeviceToHost, ix->stream), "copy out");
+    CHK(hipMemcpyAsync(out->i, di, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
+    CHK(hipMemcpyAsync(out->j, dj, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
+    CHK(hipMemcpyAsync(out->sim, ds, sizeof(float) * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
   }
-  CHK(hipStreamSynchronize(ix->stream), "copy out");
+  CHK(hipStreamSynchronize(ws.stream), "copy out");
   out->count = cnt;
   return APSS_OK;
 }
 
-// Query rows -> rank space (validated), per-row thresholds on device.
-struct QueryStage {
-  RankRows rows;
-  DBuf<float> qt;
-  std::vector<int64_t> rp_host;
-};
-
-int stage_queries(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col, const float* q_val,
-                  int on_device, const float* t_per_row, float t, QueryStage& qs) {
-  hipStream_t s = ix->stream;
+int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col,
+                  const float* q_val, int on_device, const float* t_per_row, float t, RankRows& rows) {
+  hipStream_t s = ws.stream;
   if (!ix->opts.query_safe) {
     set_error("index was built with query_safe = 0; external queries need the L2 cutoff clause");
     return APSS_EINVAL;
@@ -639,41 +563,55 @@ int stage_queries(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, const in
   }
   CsrDev in;
   int64_t nnz = 0;
-  int rc = stage_csr(ix, nq, q_row_ptr, q_col, q_val, on_device, &nnz, in);
+  int rc = stage_csr(s, nq, q_row_ptr, q_col, q_val, on_device, &nnz, in);
   if (rc) return rc;
-  DBuf<uint32_t> err;
-  DBuf<unsigned long long> bad;
-  CHK(err.alloc(1), "alloc");
-  CHK(bad.alloc(1), "alloc");
-  CHK(fill_u32(err.p, 0u, 1, s), "fill");
-  CHK(fill_u64((uint64_t*)bad.p, ~0ull, 1, s), "fill");
-  CHK(launch_check_rowptr(in.prp, nq, nnz, err.p, bad.p, s), "check row_ptr");
-  if ((rc = check_err(ix, err.p, bad.p, "query"))) return rc;
-  qs.rows.n = nq;
-  qs.rows.nnz = nnz;
-  CHK(qs.rows.rp.alloc(nq + 1), "alloc");
-  CHK(hipMemcpyAsync(qs.rows.rp.p, in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToDevice, s), "copy");
-  qs.rp_host.resize((size_t)nq + 1);
-  CHK(hipMemcpyAsync(qs.rp_host.data(), in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s), "copy");
-  CHK(qs.rows.rc.alloc(nnz), "alloc");
-  CHK(qs.rows.mw.alloc(nq), "alloc");
-  SortScratch& ss = ix->ss;
+  if ((rc = reset_err(ws))) return rc;
+  uint32_t* err = ws.err.p;
+  unsigned long long* bad = ws.bad.p;
+  CHK(launch_check_rowptr(in.prp, nq, nnz, err, bad, s), "check row_ptr");
+  if ((rc = check_err(s, err, bad, "query"))) return rc;
+  rows.n = nq;
+  rows.nnz = nnz;
+  CHK(rows.rp.reserve(nq + 1), "alloc");
+  CHK(hipMemcpyAsync(rows.rp.p, in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToDevice, s), "copy");
+  rows.rp_host.resize((size_t)nq + 1);
+  CHK(hipMemcpyAsync(rows.rp_host.data(), in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s), "copy");
+  CHK(rows.rc.reserve(nnz), "alloc");
+  CHK(rows.mw.reserve(nq), "alloc");
+  SortScratch& ss = ws.ss;
   CHK(ss.k1.reserve(nnz), "alloc");
   CHK(ss.v32a.reserve(nnz), "alloc");
   const int rbits = ceil_log2((uint64_t)ix->m);
   const int nbits = ceil_log2((uint64_t)std::max<int64_t>(nq, 1));
-  CHK(launch_query_keys(in.prp, in.pcol, in.pval, ix->rank.p, nq, ix->m, rbits, 1e-5, ss.k1.p, ss.v32a.p,
-                        qs.rows.mw.p, err.p, bad.p, s),
+  CHK(launch_query_keys(in.prp, in.pcol, in.pval, ix->rank.p, nq, ix->m, rbits, 1e-5, ss.k1.p, ss.v32a.p, rows.mw.p,
+                        err, bad, s),
       "query keys");
-  if ((rc = check_err(ix, err.p, bad.p, "query"))) return rc;
-  if ((rc = sort_rows(ix, ss.k1.p, ss.v32a.p, nnz, nbits + rbits, rbits, qs.rows.rc.p, err.p))) return rc;
-  if ((rc = check_err(ix, err.p, nullptr, "query"))) return rc;
+  if ((rc = check_err(s, err, bad, "query"))) return rc;
+  if ((rc = sort_rows(ws, ss.k1.p, ss.v32a.p, nnz, nbits + rbits, rbits, rows.rc.p, err))) return rc;
+  if ((rc = check_err(s, err, nullptr, "query"))) return rc;
   if (t_per_row) {
-    CHK(qs.qt.alloc(nq), "alloc");
-    CHK(hipMemcpyAsync(qs.qt.p, t_per_row, sizeof(float) * nq, hipMemcpyHostToDevice, s), "copy thresholds");
+    CHK(ws.qt.reserve(nq), "alloc");
+    CHK(hipMemcpyAsync(ws.qt.p, t_per_row, sizeof(float) * nq, hipMemcpyHostToDevice, s), "copy thresholds");
+    // t_per_row is borrowed: finish the copy before returning
+    CHK(hipStreamSynchronize(s), "copy thresholds");
   }
   return APSS_OK;
 }
+
+}  // namespace apss
+
+namespace {
+
+QuerySet corpus_queries(const apss_index* ix) {
+  return QuerySet{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz, ix->rows.rp_host.data()};
+}
+
+QuerySet staged_queries(const RankRows& r) {
+  return QuerySet{r.rp.p, r.rc.p, r.mw.p, r.n, r.nnz, r.rp_host.data()};
+}
+
+// Pair capacity a self-join starts with (grows on overflow).
+int64_t join_cap_hint(const apss_index* ix) { return std::max<int64_t>(1 << 20, 16 * ix->n); }
 
 }  // namespace
 
@@ -687,6 +625,7 @@ void apss_default_opts(apss_opts* o) {
   o->query_safe = 1;
   o->variant = -1;
   o->head_dims = 0;
+  o->range_rows = 0;
 }
 
 int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const float* val, int on_device,
@@ -717,13 +656,17 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
     set_error("variant %d outside [-1, %d)", o.variant, join_num_variants());
     return APSS_EINVAL;
   }
+  if (o.range_rows < 0) {
+    set_error("range_rows must be >= 0");
+    return APSS_EINVAL;
+  }
   apss_index* ix = new (std::nothrow) apss_index();
   if (!ix) {
     set_error("host allocation failed");
     return APSS_ENOMEM;
   }
   ix->opts = o;
-  ix->stream = (hipStream_t)o.stream;
+  ix->ws.stream = (hipStream_t)o.stream;
   ix->n = n;
   ix->m = m;
   ix->t_build = t_build;
@@ -732,10 +675,15 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
     const int v = atoi(ev);
     if (v >= 0 && v < join_num_variants()) ix->variant = v;
   }
+  ix->range_rows = o.range_rows > 0 ? o.range_rows : default_range_rows(ix->variant);
+  if (const char* ev = getenv("APSS_RANGE_ROWS")) {
+    const long long rr = atoll(ev);
+    if (rr > 0) ix->range_rows = rr;
+  }
   (void)hipGetDevice(&ix->device);
   int rc = build_impl(ix, row_ptr, col, val, on_device);
   if (rc) {
-    (void)hipStreamSynchronize(ix->stream);
+    (void)hipStreamSynchronize(ix->ws.stream);
     apss_index_free(ix);
     return rc;
   }
@@ -745,9 +693,7 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
 
 void apss_index_free(apss_index* idx) {
   if (!idx) return;
-  (void)hipStreamSynchronize(idx->stream);
-  for (int e = 0; e < 4; ++e)
-    if (idx->ev[e]) (void)hipEventDestroy(idx->ev[e]);
+  (void)hipStreamSynchronize(idx->ws.stream);
   delete idx;
 }
 
@@ -759,10 +705,9 @@ int apss_join_device(apss_index* ix, float t, uint32_t* out_i, uint32_t* out_j, 
   }
   int rc = check_t(ix, t);
   if (rc) return rc;
-  QuerySet Q{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz, ix->rp_host.data()};
   int64_t cnt = 0;
-  if ((rc = run_join(ix, Q, 1, t, nullptr, &cnt))) return rc;
-  return finish_device(ix, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count);
+  if ((rc = run_join(ix, ix->ws, corpus_queries(ix), 1, t, nullptr, join_cap_hint(ix), &cnt))) return rc;
+  return finish_device(ix->ws, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count);
 }
 
 int apss_join(apss_index* ix, float t, apss_pairs* out) {
@@ -775,10 +720,9 @@ int apss_join(apss_index* ix, float t, apss_pairs* out) {
   out->sim = nullptr;
   int rc = check_t(ix, t);
   if (rc) return rc;
-  QuerySet Q{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz, ix->rp_host.data()};
   int64_t cnt = 0;
-  if ((rc = run_join(ix, Q, 1, t, nullptr, &cnt))) return rc;
-  return finish_host(ix, cnt, ceil_log2((uint64_t)ix->n), out);
+  if ((rc = run_join(ix, ix->ws, corpus_queries(ix), 1, t, nullptr, join_cap_hint(ix), &cnt))) return rc;
+  return finish_host(ix->ws, cnt, ceil_log2((uint64_t)ix->n), out);
 }
 
 int apss_query_device(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col, const float* q_val,
@@ -789,13 +733,13 @@ int apss_query_device(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, cons
     set_error("NULL or invalid argument");
     return APSS_EINVAL;
   }
-  QueryStage qs;
-  int rc = stage_queries(ix, nq, q_row_ptr, q_col, q_val, on_device, t_per_row, t, qs);
+  RankRows rows;
+  int rc = stage_queries(ix, ix->ws, nq, q_row_ptr, q_col, q_val, on_device, t_per_row, t, rows);
   if (rc) return rc;
-  QuerySet Q{qs.rows.rp.p, qs.rows.rc.p, qs.rows.mw.p, nq, qs.rows.nnz, qs.rp_host.data()};
   int64_t cnt = 0;
-  if ((rc = run_join(ix, Q, 0, t, t_per_row ? qs.qt.p : nullptr, &cnt))) return rc;
-  return finish_device(ix, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count);
+  if ((rc = run_join(ix, ix->ws, staged_queries(rows), 0, t, t_per_row ? ix->ws.qt.p : nullptr, 16 * nq, &cnt)))
+    return rc;
+  return finish_device(ix->ws, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count);
 }
 
 int apss_query(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col, const float* q_val,
@@ -807,13 +751,13 @@ int apss_query(apss_index* ix, int64_t nq, const int64_t* q_row_ptr, const int32
   out->count = 0;
   out->i = out->j = nullptr;
   out->sim = nullptr;
-  QueryStage qs;
-  int rc = stage_queries(ix, nq, q_row_ptr, q_col, q_val, on_device, t_per_row, t, qs);
+  RankRows rows;
+  int rc = stage_queries(ix, ix->ws, nq, q_row_ptr, q_col, q_val, on_device, t_per_row, t, rows);
   if (rc) return rc;
-  QuerySet Q{qs.rows.rp.p, qs.rows.rc.p, qs.rows.mw.p, nq, qs.rows.nnz, qs.rp_host.data()};
   int64_t cnt = 0;
-  if ((rc = run_join(ix, Q, 0, t, t_per_row ? qs.qt.p : nullptr, &cnt))) return rc;
-  return finish_host(ix, cnt, ceil_log2((uint64_t)ix->n), out);
+  if ((rc = run_join(ix, ix->ws, staged_queries(rows), 0, t, t_per_row ? ix->ws.qt.p : nullptr, 16 * nq, &cnt)))
+    return rc;
+  return finish_host(ix->ws, cnt, ceil_log2((uint64_t)ix->n), out);
 }
 
 void apss_pairs_free(apss_pairs* p) {
@@ -831,7 +775,7 @@ int apss_last_stats(const apss_index* ix, apss_stats* out) {
     set_error("NULL argument");
     return APSS_EINVAL;
   }
-  *out = ix->last;
+  *out = ix->ws.last;
   return APSS_OK;
 }
 
@@ -840,7 +784,7 @@ int apss_index_export(const apss_index* ix, int32_t* rank, float* maxweight, int
     set_error("NULL argument");
     return APSS_EINVAL;
   }
-  hipStream_t s = ix->stream;
+  hipStream_t s = ix->ws.stream;
   if (rank) CHK(hipMemcpyAsync(rank, ix->rank.p, sizeof(int32_t) * ix->m, hipMemcpyDeviceToHost, s), "export");
   std::vector<float> mwr;
   std::vector<int32_t> inv;

@@ -1,0 +1,162 @@
+// Host-side internals of the apss library shared by the C ABI (capi.cpp)
+// and the serving loop (server.cpp).  Not part of the ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/apss.h"
+#include "apss_internal.h"
+
+namespace apss {
+
+// Owned device allocation.
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  int64_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t alloc(int64_t count) {
+    release();
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc((void**)&p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    n = count;
+    return hipSuccess;
+  }
+  // grow without preserving contents
+  hipError_t reserve(int64_t count) {
+    if (count <= n && p) return hipSuccess;
+    return alloc(count);
+  }
+  int64_t bytes() const { return p ? n * (int64_t)sizeof(T) : 0; }
+};
+
+// Rank-space rows of a query set (the corpus itself for the self-join).
+struct RankRows {
+  int64_t n = 0, nnz = 0;
+  DBuf<int64_t> rp;
+  DBuf<RComp> rc;
+  DBuf<float> mw;
+  std::vector<int64_t> rp_host;  // host copy of rp (tile formation)
+};
+
+// Sort scratch sized for the largest sort done so far.
+struct SortScratch {
+  DBuf<uint64_t> k1, k2, v64a, v64b;
+  DBuf<uint32_t> v32a, v32b;
+  DBuf<int64_t> hist, scan;
+  int64_t bytes() const {
+    return k1.bytes() + k2.bytes() + v64a.bytes() + v64b.bytes() + v32a.bytes() + v32b.bytes() + hist.bytes() +
+           scan.bytes();
+  }
+};
+
+// Everything one join or query call needs besides the index: its stream,
+// scratch, raw output and timing.  The index has one for apss_join and
+// apss_query; every slot of a server has its own, so calls on different
+// workspaces may run at the same time.
+struct Workspace {
+  hipStream_t stream = nullptr;
+  SortScratch ss;
+  DBuf<int64_t> tstart, qcum;
+  DBuf<unsigned int> qctr;
+  DBuf<uint32_t> wg_cur;
+  DBuf<unsigned long long> counters;
+  DBuf<uint64_t> raw_key;
+  DBuf<float> raw_sim;
+  DBuf<float> qt;
+  DBuf<uint32_t> err;
+  DBuf<unsigned long long> bad;
+  apss_stats last;
+  int64_t regrows = 0;  // joins rerun because the pair buffer was too small
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  ~Workspace() {
+    for (int e = 0; e < 4; ++e)
+      if (ev[e]) (void)hipEventDestroy(ev[e]);
+  }
+  int64_t bytes() const {
+    return ss.bytes() + tstart.bytes() + qcum.bytes() + qctr.bytes() + wg_cur.bytes() + counters.bytes() +
+           raw_key.bytes() + raw_sim.bytes() + qt.bytes();
+  }
+};
+
+}  // namespace apss
+
+struct apss_index {
+  int device = 0;
+  apss_opts opts;
+  int64_t n = 0, m = 0, nnz = 0, P = 0;
+  float t_build = 0.0f;
+  int32_t H = 0;
+  int variant = 1;          // tile variant of the join kernel
+  int64_t range_rows = 0;   // corpus rows per work-item range
+  apss::RankRows rows;  // corpus rows in rank space (densest dimension first)
+  apss::DBuf<apss::RowStat> rs;
+  apss::DBuf<int32_t> rank, inv;
+  apss::DBuf<float> mw_r;  // maxweight by rank
+  apss::DBuf<int64_t> off;
+  apss::DBuf<apss::Post> post;
+  apss::DBuf<uint32_t> post4;  // packed copy of post for streaming
+  // lazily built tables (guarded by prep_mu)
+  std::mutex prep_mu;
+  apss::DBuf<uint32_t> hoff[2];  // per-block offsets of the dense lists (block width 1024, 2048)
+  int64_t hoff_nb[2] = {0, 0};
+  apss::DBuf<uint32_t> toff;  // per-range offsets of the sparse lists
+  int64_t toff_rows = 0, toff_nR = 0;
+  int grid[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  apss::Workspace ws;  // for apss_join / apss_query
+};
+
+namespace apss {
+
+struct QuerySet {
+  const int64_t* rp;  // device
+  const RComp* rc;
+  const float* mw;
+  int64_t n, nnz;
+  const int64_t* rp_host;  // host copy of rp
+};
+
+std::string& last_error();  // per calling thread
+void set_error(const char* fmt, ...);
+int dev_err(hipError_t e, const char* what);
+int check_t(const apss_index* ix, float t);
+// Make the lookup tables of a tile variant and range width ready (built on
+// stream s, finished before return); safe to call from several threads.
+// Rebuilding the range table for another width while a join runs is not.
+int prepare(apss_index* ix, hipStream_t s, int variant, int64_t range_rows);
+int64_t default_range_rows(int variant);
+// Query rows -> rank space on ws's stream (validates; t_per_row is host memory or NULL).
+int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col,
+                  const float* q_val, int on_device, const float* t_per_row, float t, RankRows& rows);
+// Run the join kernels; sorted raw pairs in ws.raw_key / ws.raw_sim; count in
+// *count.  cap_hint: pair capacity to start with (grown and rerun on overflow).
+int run_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, float t, const float* qt_dev,
+             int64_t cap_hint, int64_t* count);
+// Unpack the sorted raw pairs into device arrays / library-owned host arrays.
+int finish_device(Workspace& ws, int64_t cnt, int bj, uint32_t* out_i, uint32_t* out_j, float* out_sim,
+                  int64_t capacity, int64_t* count);
+int finish_host(Workspace& ws, int64_t cnt, int bj, apss_pairs* out);
+
+}  // namespace apss
+
+#define APSS_CHK(expr, what)                               \
+  do {                                                     \
+    hipError_t e__ = (expr);                               \
+    if (e__ != hipSuccess) return ::apss::dev_err(e__, what); \
+  } while (0)
