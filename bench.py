@@ -79,6 +79,28 @@ def cpu_baseline(V, t, budget_s: float):
     }
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("join.hip", "join.h", "apss_internal.h"):
+        with open(os.path.join(ROOT, "paper_1402_3010_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config, t, n):
+    """HBM bytes per k_join launch from the committed counter summary, if it
+    was taken on this workload and on the kernel source as it is now."""
+    path = os.path.join(ROOT, "profiles", "k_join_%s_traffic.json" % config)
+    if n is not None or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash() or abs(rec.get("t", -1) - float(t)) > 1e-6:
+        return None
+    return rec["traffic_bytes"]
+
+
 def percentile(x, q):
     x = sorted(x)
     if not x:
@@ -352,8 +374,10 @@ def main():
         "band_rescored": stats["band"],
         "index_build_s": build_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "k_join", "kernel_ms": kms, "algorithmic_bytes": alg_bytes},
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(args.config, t, args.n),
+                     "kernel": "k_join", "kernel_ms": kms, "algorithmic_bytes": alg_bytes,
+                     "traffic_source": "profiles/k_join_%s_traffic.md" % args.config},
     }
     ix.close()
     if not args.no_cpu_baseline:
