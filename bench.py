@@ -31,6 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0  # dense bf16 MFMA
 WORKLOADS = {
     "c1": "n=2,000 m=10,000 nnz/vector uniform 10..60, Zipf s=1.0, t=0.5",
     "c2": "n=100,000 m=200,000 nnz/vector lognormal mean 80 (5..2000), Zipf s=1.1",
@@ -162,6 +163,70 @@ class ServeDriver:
         return out, elapsed, busy
 
 
+def screen_bench(args):
+    """c4: the plain join and the screened join (bf16 MFMA head screen over the
+    4,096 densest dimensions + sparse pass) on the same corpus and GPU; the
+    outputs must be identical."""
+    import numpy as np
+    import torch
+
+    import paper_1402_3010_amd as apss
+    from synth.corpus import CONFIGS, make_corpus, spec_for
+
+    spec = spec_for("c4", n=args.screen_n)
+    V = make_corpus(spec)
+    t = np.float32(CONFIGS["c4"]["t"][0])
+    log("screen corpus c4: n=%d nnz=%d t=%.2f" % (V.n, V.nnz, t))
+    dev = (V.n, V.m, torch.from_numpy(V.row_ptr).cuda(), torch.from_numpy(V.col).cuda(),
+           torch.from_numpy(V.val).cuda())
+    res = {}
+    outs = {}
+    for mode, sd in (("plain", 0), ("screened", args.screen_dims)):
+        ix = apss.Index.build(dev, t, screen_dims=sd)
+        torch.cuda.synchronize()
+        i0, _, _ = ix.join(t)
+        cap = len(i0) + 1024
+        oi = torch.empty(cap, dtype=torch.int32, device="cuda")
+        oj = torch.empty(cap, dtype=torch.int32, device="cuda")
+        osim = torch.empty(cap, dtype=torch.float32, device="cuda")
+        ix.join_device(t, oi, oj, osim)  # warm-up
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.screen_steps):
+            t0 = time.perf_counter()
+            cnt = ix.join_device(t, oi, oj, osim)
+            torch.cuda.synchronize()
+            ms.append(1000.0 * (time.perf_counter() - t0))
+        st = ix.stats()
+        outs[mode] = (oi[:cnt].cpu().numpy(), oj[:cnt].cpu().numpy(), osim[:cnt].cpu().numpy())
+        res[mode] = {"ms": float(np.median(ms)), "matches": cnt, "stats": st}
+        log("%s join: %.1f ms, %d pairs" % (mode, res[mode]["ms"], cnt))
+        ix.close()
+        del oi, oj, osim
+    a, b = outs["plain"], outs["screened"]
+    identical = (len(a[0]) == len(b[0]) and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+                 and np.array_equal(a[2].view(np.uint32), b[2].view(np.uint32)))
+    st = res["screened"]["stats"]
+    flops = 2.0 * st["screen_tiles"] * 128 * 128 * st["screen_ld"]
+    tflops = flops / (st["ms_screen"] / 1000.0) / 1e12 if st["ms_screen"] > 0 else 0.0
+    return {
+        "workload": "c4: n=%d m=%d nnz/vector lognormal mean 150 (5..2000), Zipf s=0.9, t=%.1f; head = %d densest "
+                    "dimensions as bf16" % (V.n, V.m, float(t), args.screen_dims),
+        "plain_ms": res["plain"]["ms"], "screened_ms": res["screened"]["ms"],
+        "speedup": res["plain"]["ms"] / res["screened"]["ms"], "identical_output": bool(identical),
+        "matches": res["screened"]["matches"],
+        "plain_posting_visits": res["plain"]["stats"]["posting_visits"],
+        "sparse_pass_posting_visits": st["posting_visits"], "sparse_pass_ms": st["ms_candidates"],
+        "sparse_pass_candidates": st["candidates"], "sparse_pass_survivors": st["bound_survivors"],
+        "sparse_pass_verified": st["verified"], "plain_candidates": res["plain"]["stats"]["candidates"],
+        "plain_survivors": res["plain"]["stats"]["bound_survivors"], "plain_ms_kernel": res["plain"]["stats"]["ms_candidates"],
+        "screen_rows": st["screen_rows"], "screen_tiles": st["screen_tiles"],
+        "screen_candidates": st["screen_candidates"], "screen_ms": st["ms_screen"],
+        "mfma_roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                          "frac": tflops / PEAK_BF16_TFLOPS, "kernel": "k_screen_mfma", "flops": flops},
+    }
+
+
 def serve_bench(args):
     import numpy as np
     import torch
@@ -266,6 +331,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--no-screen", action="store_true", help="skip the screened-join comparison")
+    ap.add_argument("--screen-only", action="store_true")
+    ap.add_argument("--screen-n", type=int, default=None)
+    ap.add_argument("--screen-dims", type=int, default=4096)
+    ap.add_argument("--screen-steps", type=int, default=3)
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-n", type=int, default=None, help="fewer corpus rows for the serving workload")
     ap.add_argument("--serve-slots", type=int, default=2)
@@ -302,6 +372,9 @@ def main():
     torch.cuda.set_device(0)
     if args.serve_only:
         print(json.dumps({"serve": serve_bench(args)}), flush=True)
+        return
+    if args.screen_only:
+        print(json.dumps({"screen": screen_bench(args)}), flush=True)
         return
     t = np.float32(args.t if args.t is not None else CONFIGS[args.config]["t"][0])
     spec = spec_for(args.config, n=args.n)
@@ -384,6 +457,8 @@ def main():
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(V, t, args.cpu_budget)
     del V
+    if not args.no_screen:
+        out["screen"] = screen_bench(args)
     if not args.no_serve:
         sv = serve_bench(args)
         out["serve"] = sv

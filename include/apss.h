@@ -67,6 +67,9 @@ typedef struct {
   int32_t range_rows;    /* corpus rows per work item of the join (rounded down to a multiple of the
                             variant's block rows; 0 = default 8192).  The environment variable
                             APSS_RANGE_ROWS overrides it. */
+  int32_t screen_dims;   /* > 0 (at most 8192): apss_join / apss_join_device use the screened join
+                            with this many densest dimensions as the dense head (bf16 MFMA screen
+                            plus a sparse pass over the rest); 0 (default): plain join only */
   int32_t reserved[8];
 } apss_opts;
 
@@ -134,6 +137,12 @@ typedef struct {
   int64_t matches;          /* pairs returned */
   double ms_candidates;     /* device time of the candidate/filter/verify kernel */
   double ms_total;          /* device time of the whole call (kernels + sort) */
+  /* screened join only (zero otherwise) */
+  int64_t screen_rows;        /* rows whose head norm reaches t */
+  int64_t screen_tiles;       /* 128 x 128 tiles of the head screen (each 2 * 128 * 128 * ld flops) */
+  int64_t screen_candidates;  /* pairs passing the screen's widened threshold */
+  int64_t screen_ld;          /* head dimensions padded to the screen's K step */
+  double ms_screen;           /* device time of the screen's MFMA kernel */
 } apss_stats;
 
 int apss_last_stats(const apss_index* idx, apss_stats* out);

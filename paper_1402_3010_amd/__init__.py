@@ -40,7 +40,7 @@ class ApssError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("stream", ctypes.c_void_p), ("query_safe", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("head_dims", ctypes.c_int32), ("range_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("screen_dims", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
 
 
 class Pairs(ctypes.Structure):
@@ -51,7 +51,9 @@ class Pairs(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("posting_visits", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("bound_survivors", ctypes.c_int64), ("verified", ctypes.c_int64), ("band", ctypes.c_int64),
-                ("matches", ctypes.c_int64), ("ms_candidates", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("matches", ctypes.c_int64), ("ms_candidates", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("screen_rows", ctypes.c_int64), ("screen_tiles", ctypes.c_int64),
+                ("screen_candidates", ctypes.c_int64), ("screen_ld", ctypes.c_int64), ("ms_screen", ctypes.c_double)]
 
 
 SERVER_MAX_SLOTS = 8
@@ -188,7 +190,7 @@ def current_stream_handle() -> Optional[int]:
 
 
 def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, variant: int = -1,
-                 range_rows: int = 0) -> Opts:
+                 range_rows: int = 0, screen_dims: int = 0) -> Opts:
     o = Opts()
     load().apss_default_opts(ctypes.byref(o))
     o.stream = stream
@@ -196,6 +198,7 @@ def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, varia
     o.head_dims = head_dims
     o.variant = variant
     o.range_rows = range_rows
+    o.screen_dims = screen_dims
     return o
 
 
@@ -309,7 +312,7 @@ class Index:
 
     @classmethod
     def build(cls, V, t_build: float, stream=None, query_safe: bool = True, head_dims: int = 0,
-              on_device: bool = False, variant: int = -1, range_rows: int = 0) -> "Index":
+              on_device: bool = False, variant: int = -1, range_rows: int = 0, screen_dims: int = 0) -> "Index":
         """V: object with n, m, row_ptr, col, val (numpy), or a tuple (n, m, row_ptr, col, val) of tensors."""
         if isinstance(V, tuple):
             n, m, rp, col, val = V
@@ -322,7 +325,8 @@ class Index:
             val = torch.from_numpy(np.ascontiguousarray(val, np.float32)).cuda()
         if stream is None:
             stream = current_stream_handle()
-        h = build_index(n, m, rp, col, val, t_build, default_opts(stream, query_safe, head_dims, variant, range_rows))
+        h = build_index(n, m, rp, col, val, t_build, default_opts(stream, query_safe, head_dims, variant, range_rows,
+                                                                      screen_dims))
         return cls(h, int(n), int(m))
 
     def join(self, t: float):

@@ -16,6 +16,7 @@
 #include "index_build.h"
 #include "join.h"
 #include "lib.h"
+#include "screen.h"
 
 namespace apss {
 
@@ -153,6 +154,8 @@ int stage_csr(hipStream_t s, int64_t n, const int64_t* row_ptr, const int32_t* c
 
 int hoff_slot(int cb) { return cb == 1024 ? 0 : 1; }
 
+int build_lists(apss_index* ix);
+
 int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const float* val, int on_device) {
   Workspace& ws = ix->ws;
   hipStream_t s = ws.stream;
@@ -211,6 +214,18 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   CHK(ix->rows.rc.alloc(nnz), "alloc");
   if ((rc = sort_rows(ws, ss.k1.p, ss.v32a.p, nnz, nbits + rbits, rbits, ix->rows.rc.p, err))) return rc;
   if ((rc = check_err(s, err, nullptr, "build_index"))) return rc;
+  return build_lists(ix);
+}
+
+// From the rank-space rows on: cutoff of every row, the inverted lists of
+// the indexed parts and the lookup tables of the join.
+int build_lists(apss_index* ix) {
+  Workspace& ws = ix->ws;
+  hipStream_t s = ws.stream;
+  SortScratch& ss = ws.ss;
+  const int64_t n = ix->n, m = ix->m;
+  const int rbits = ceil_log2((uint64_t)m);
+  int rc = APSS_OK;
 
   // cutoff of the unindexed part
   CHK(ix->rs.alloc(n), "alloc");
@@ -219,8 +234,8 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   CHK(nidx.alloc(n + 1), "alloc");
   CHK(scan_tmp.alloc(scan_tmp_elems(n + 1)), "alloc");
   CHK(total.alloc(1), "alloc");
-  CHK(launch_cutoff(ix->rows.rp.p, ix->rows.rc.p, ix->mw_r.p, n, ix->t_build, ix->opts.query_safe ? 1 : 0, ix->rs.p,
-                    ix->rows.mw.p, nidx.p, s),
+  CHK(launch_cutoff(ix->rows.rp.p, ix->rows.rc.p, ix->mw_r.p, n, ix->t_build, ix->opts.query_safe ? 1 : 0,
+                    ix->head_cut, ix->rs.p, ix->rows.mw.p, nidx.p, s),
       "cutoff");
   CHK(exclusive_scan_i64(nidx.p, n, scan_tmp.p, total.p, s), "scan");
   int64_t P = 0;
@@ -268,6 +283,45 @@ int build_impl(apss_index* ix, const int64_t* row_ptr, const int32_t* col, const
   ss.v32a.release();
   ss.v32b.release();
   return APSS_OK;
+}
+
+template <typename T>
+int copy_buf(DBuf<T>& dst, const DBuf<T>& src, int64_t count, hipStream_t s) {
+  CHK(dst.alloc(count), "alloc");
+  if (count > 0) CHK(hipMemcpyAsync(dst.p, src.p, sizeof(T) * count, hipMemcpyDeviceToDevice, s), "copy");
+  return APSS_OK;
+}
+
+// The head-cut index of the screened join: the same rank-space rows, with
+// every row's unindexed part set to its components of rank < head.
+int build_screen(apss_index* ix, int32_t head) {
+  apss_index* sx = new (std::nothrow) apss_index();
+  if (!sx) {
+    set_error("host allocation failed");
+    return APSS_ENOMEM;
+  }
+  ix->screen = sx;
+  hipStream_t s = ix->ws.stream;
+  sx->device = ix->device;
+  sx->opts = ix->opts;
+  sx->opts.screen_dims = 0;
+  sx->ws.stream = s;
+  sx->n = ix->n;
+  sx->m = ix->m;
+  sx->nnz = ix->nnz;
+  sx->t_build = ix->t_build;
+  sx->variant = ix->variant;
+  sx->range_rows = ix->range_rows;
+  sx->head_cut = head;
+  sx->rows.n = ix->rows.n;
+  sx->rows.nnz = ix->rows.nnz;
+  sx->rows.rp_host = ix->rows.rp_host;
+  int rc;
+  if ((rc = copy_buf(sx->rows.rp, ix->rows.rp, ix->n + 1, s))) return rc;
+  if ((rc = copy_buf(sx->rows.rc, ix->rows.rc, ix->nnz, s))) return rc;
+  if ((rc = copy_buf(sx->mw_r, ix->mw_r, ix->m, s))) return rc;
+  CHK(sx->rows.mw.alloc(ix->n), "alloc");
+  return build_lists(sx);
 }
 
 // Query tiles: consecutive queries, at most QT of them and, unless a single
@@ -339,15 +393,18 @@ int prepare(apss_index* ix, hipStream_t s, int variant, int64_t range_rows) {
   return APSS_OK;
 }
 
-int run_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, float t, const float* qt_dev,
-             int64_t cap_hint, int64_t* count) {
+// Host-side preparation of one join kernel launch: tiles, work queues and
+// cursor space on ws's stream.  Output buffers and counters are set at launch.
+struct JoinPlan {
+  JoinArgs a{};
+  int variant = 0;
+  int G = 0;
+  int bi = 0, bj = 0;
+};
+
+int plan_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, float t, const float* qt_dev,
+              const RowStat* qrs, JoinPlan& P) {
   hipStream_t s = ws.stream;
-  memset(&ws.last, 0, sizeof(ws.last));
-  *count = 0;
-  for (int e = 0; e < 4; ++e)
-    if (!ws.ev[e]) CHK(hipEventCreateWithFlags(&ws.ev[e], hipEventDefault), "event");
-  CHK(hipEventRecord(ws.ev[0], s), "event");
-  if (Q.n == 0 || ix->n == 0) return APSS_OK;
   const int variant = ix->variant;
   int QT = 0, CB = 0;
   if (join_variant_geometry(variant, &QT, &CB)) {
@@ -392,86 +449,267 @@ int run_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, flo
   // per-workgroup cursor space for tiles too large to stage in LDS
   const int64_t wg_stride = 2 * std::max<int64_t>(tiles.max_nnz, 1);
   CHK(ws.wg_cur.reserve((int64_t)G * wg_stride), "alloc cursors");
-  if (ws.raw_key.n < cap_hint || !ws.raw_key.p) {
-    const int64_t cap0 = std::max<int64_t>(cap_hint, 1 << 16);
-    CHK(ws.raw_key.alloc(cap0), "alloc pairs");
-    CHK(ws.raw_sim.alloc(cap0), "alloc pairs");
+  JoinArgs& a = P.a;
+  a = JoinArgs{};
+  a.rp = ix->rows.rp.p;
+  a.rc = ix->rows.rc.p;
+  a.rs = ix->rs.p;
+  a.off = ix->off.p;
+  a.post = ix->post.p;
+  a.post4 = ix->post4.p;
+  a.post4_bytes = (uint32_t)(4 * (ix->P + 1));
+  a.hoff = ix->hoff[slot].p;
+  a.H = ix->H;
+  a.nb = nb;
+  a.n = ix->n;
+  a.qrp = Q.rp;
+  a.qrc = Q.rc;
+  a.qmw = Q.mw;
+  a.qrs = qrs;
+  a.qt = qt_dev;
+  a.t = t;
+  a.nq = Q.n;
+  a.triangle = triangle;
+  a.ntiles = ntiles;
+  a.tstart = ws.tstart.p;
+  a.toff = ix->toff.p;
+  a.m_tail = (int32_t)(ix->m - ix->H);
+  a.K = K;
+  a.nrx = nrx;
+  a.qcum = ws.qcum.p;
+  a.qctr = ws.qctr.p;
+  a.wg_cur = ws.wg_cur.p;
+  a.wg_cur_stride = wg_stride;
+  P.variant = variant;
+  P.G = G;
+  P.bj = ceil_log2((uint64_t)ix->n);
+  P.bi = ceil_log2((uint64_t)(triangle ? ix->n : Q.n));
+  a.bj = P.bj;
+  return APSS_OK;
+}
+
+// Launch a planned join writing pairs into ws.raw_key / raw_sim through ws.counters.
+int launch_planned(Workspace& ws, JoinPlan& P) {
+  JoinArgs& a = P.a;
+  a.out_key = ws.raw_key.p;
+  a.out_sim = ws.raw_sim.p;
+  a.cap = ws.raw_key.n;
+  a.counters = ws.counters.p;
+  a.qctr = ws.qctr.p;
+  CHK(fill_u32(ws.qctr.p, 0u, 8, ws.stream), "fill");
+  if (!join_args_complete(a)) {
+    set_error("internal: join launched with a missing device buffer");
+    return APSS_EDEVICE;
   }
-  const int bj = ceil_log2((uint64_t)ix->n);
-  const int bi = ceil_log2((uint64_t)(triangle ? ix->n : Q.n));
+  CHK(launch_join(a, P.variant, P.G, ws.stream), "join kernel");
+  return APSS_OK;
+}
+
+int ensure_pair_capacity(Workspace& ws, int64_t cap) {
+  if (ws.raw_key.p && ws.raw_key.n >= cap) return APSS_OK;
+  cap = std::max<int64_t>(cap, 1 << 16);
+  CHK(ws.raw_key.alloc(cap), "alloc pairs");
+  CHK(ws.raw_sim.alloc(cap), "alloc pairs");
+  return APSS_OK;
+}
+
+int sort_pairs(Workspace& ws, int64_t matches, int key_bits) {
+  SortScratch& ss = ws.ss;
+  CHK(ss.k2.reserve(matches), "alloc sort");
+  CHK(ss.v32b.reserve(matches), "alloc sort");
+  CHK(ss.hist.reserve(radix_hist_elems(matches)), "alloc sort");
+  CHK(ss.scan.reserve(radix_scan_tmp_elems(matches)), "alloc sort");
+  CHK(radix_sort_u64_u32(ws.raw_key.p, (uint32_t*)ws.raw_sim.p, ss.k2.p, ss.v32b.p, matches, key_bits, ss.hist.p,
+                         ss.scan.p, ws.stream),
+      "pair sort");
+  return APSS_OK;
+}
+
+void take_counters(Workspace& ws, const unsigned long long* c) {
+  ws.last.posting_visits = (int64_t)(c[C_VISITS] + c[C_TAILVISITS]);
+  ws.last.candidates = (int64_t)c[C_CANDIDATES];
+  ws.last.bound_survivors = (int64_t)c[C_SURVIVORS];
+  ws.last.verified = (int64_t)c[C_VERIFIED];
+  ws.last.band = (int64_t)c[C_BAND];
+  ws.last.matches = (int64_t)c[C_MATCHES];
+}
+
+int start_call(Workspace& ws) {
+  memset(&ws.last, 0, sizeof(ws.last));
+  for (int e = 0; e < 6; ++e)
+    if (!ws.ev[e]) CHK(hipEventCreateWithFlags(&ws.ev[e], hipEventDefault), "event");
+  CHK(hipEventRecord(ws.ev[0], ws.stream), "event");
+  return APSS_OK;
+}
+
+int run_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, float t, const float* qt_dev,
+             int64_t cap_hint, int64_t* count) {
+  hipStream_t s = ws.stream;
+  *count = 0;
+  int rc = start_call(ws);
+  if (rc) return rc;
+  if (Q.n == 0 || ix->n == 0) return APSS_OK;
+  JoinPlan P;
+  if ((rc = plan_join(ix, ws, Q, triangle, t, qt_dev, nullptr, P))) return rc;
+  if ((rc = ensure_pair_capacity(ws, cap_hint))) return rc;
   for (int attempt = 0; attempt < 2; ++attempt) {
     CHK(fill_u64((uint64_t*)ws.counters.p, 0ull, C_NUM, s), "fill");
-    CHK(fill_u32(ws.qctr.p, 0u, 8, s), "fill");
-    JoinArgs a;
-    a.rp = ix->rows.rp.p;
-    a.rc = ix->rows.rc.p;
-    a.rs = ix->rs.p;
-    a.off = ix->off.p;
-    a.post = ix->post.p;
-    a.post4 = ix->post4.p;
-    a.post4_bytes = (uint32_t)(4 * (ix->P + 1));
-    a.hoff = ix->hoff[slot].p;
-    a.H = ix->H;
-    a.nb = nb;
-    a.n = ix->n;
-    a.qrp = Q.rp;
-    a.qrc = Q.rc;
-    a.qmw = Q.mw;
-    a.qt = qt_dev;
-    a.t = t;
-    a.nq = Q.n;
-    a.triangle = triangle;
-    a.ntiles = ntiles;
-    a.tstart = ws.tstart.p;
-    a.toff = ix->toff.p;
-    a.m_tail = (int32_t)(ix->m - ix->H);
-    a.K = K;
-    a.nrx = nrx;
-    a.qcum = ws.qcum.p;
-    a.qctr = ws.qctr.p;
-    a.wg_cur = ws.wg_cur.p;
-    a.wg_cur_stride = wg_stride;
-    a.out_key = ws.raw_key.p;
-    a.out_sim = ws.raw_sim.p;
-    a.cap = ws.raw_key.n;
-    a.bj = bj;
-    a.counters = ws.counters.p;
     CHK(hipEventRecord(ws.ev[1], s), "event");
-    if (!join_args_complete(a)) {
-      set_error("internal: join launched with a missing device buffer");
-      return APSS_EDEVICE;
-    }
-    CHK(launch_join(a, variant, G, s), "join kernel");
+    if ((rc = launch_planned(ws, P))) return rc;
     CHK(hipEventRecord(ws.ev[2], s), "event");
     unsigned long long c[C_NUM];
     CHK(hipMemcpyAsync(c, ws.counters.p, sizeof(c), hipMemcpyDeviceToHost, s), "read counters");
     CHK(hipStreamSynchronize(s), "join");
     const int64_t matches = (int64_t)c[C_MATCHES];
     if (matches > ws.raw_key.n) {
-      const int64_t cap = matches + matches / 8 + 1024;
-      CHK(ws.raw_key.alloc(cap), "alloc pairs");
-      CHK(ws.raw_sim.alloc(cap), "alloc pairs");
+      if ((rc = ensure_pair_capacity(ws, matches + matches / 8 + 1024))) return rc;
       ++ws.regrows;
       continue;  // rerun with room for every pair
     }
-    ws.last.posting_visits = (int64_t)(c[C_VISITS] + c[C_TAILVISITS]);
-    ws.last.candidates = (int64_t)c[C_CANDIDATES];
-    ws.last.bound_survivors = (int64_t)c[C_SURVIVORS];
-    ws.last.verified = (int64_t)c[C_VERIFIED];
-    ws.last.band = (int64_t)c[C_BAND];
-    ws.last.matches = matches;
+    take_counters(ws, c);
     float ms = 0.0f;
     CHK(hipEventElapsedTime(&ms, ws.ev[1], ws.ev[2]), "event");
     ws.last.ms_candidates = ms;
-    // sort by key
+    if ((rc = sort_pairs(ws, matches, P.bi + P.bj))) return rc;
+    *count = matches;
+    return APSS_OK;
+  }
+  set_error("pair buffer kept overflowing");
+  return APSS_ENOMEM;
+}
+
+// Screened self-join: the bf16 MFMA head screen (pairs that share no tail
+// dimension) and the sparse pass over the head-cut index (pairs that share
+// one), written into one pair buffer and sorted together.
+int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, int64_t* count) {
+  apss_index* sx = ix->screen;
+  hipStream_t s = ws.stream;
+  *count = 0;
+  int rc = start_call(ws);
+  if (rc) return rc;
+  const int64_t n = sx->n;
+  if (n == 0) return APSS_OK;
+  const int32_t head = sx->head_cut;
+  const int32_t ld = (int32_t)((head + kScreenK - 1) / kScreenK * kScreenK);
+  const int bj = ceil_log2((uint64_t)n);
+
+  // rows whose head norm reaches t, by decreasing head norm
+  CHK(ws.s_keys.reserve(n), "alloc screen");
+  CHK(ws.s_cnt.reserve(1), "alloc screen");
+  CHK(fill_u64((uint64_t*)ws.s_cnt.p, 0ull, 1, s), "fill");
+  CHK(launch_screen_select(sx->rs.p, n, t, ws.s_keys.p, ws.s_cnt.p, s), "screen select");
+  unsigned long long S64 = 0;
+  CHK(hipMemcpyAsync(&S64, ws.s_cnt.p, sizeof(S64), hipMemcpyDeviceToHost, s), "screen select");
+  CHK(hipStreamSynchronize(s), "screen select");
+  const int64_t S = (int64_t)S64;
+  const int64_t Sp = (S + kScreenTile - 1) / kScreenTile * kScreenTile;
+  int64_t nc = 0, ntiles = 0;
+  if (S > 1) {
     SortScratch& ss = ws.ss;
-    CHK(ss.k2.reserve(matches), "alloc sort");
-    CHK(ss.v32b.reserve(matches), "alloc sort");
-    CHK(ss.hist.reserve(radix_hist_elems(matches)), "alloc sort");
-    CHK(ss.scan.reserve(radix_scan_tmp_elems(matches)), "alloc sort");
-    CHK(radix_sort_u64_u32(ws.raw_key.p, (uint32_t*)ws.raw_sim.p, ss.k2.p, ss.v32b.p, matches, bi + bj, ss.hist.p,
-                           ss.scan.p, s),
-        "pair sort");
+    CHK(ss.k2.reserve(S), "alloc sort");
+    CHK(ss.v32a.reserve(S), "alloc sort");
+    CHK(ss.v32b.reserve(S), "alloc sort");
+    CHK(ss.hist.reserve(radix_hist_elems(S)), "alloc sort");
+    CHK(ss.scan.reserve(radix_scan_tmp_elems(S)), "alloc sort");
+    CHK(radix_sort_u64_u32(ws.s_keys.p, ss.v32a.p, ss.k2.p, ss.v32b.p, S, 64, ss.hist.p, ss.scan.p, s), "screen sort");
+    CHK(ws.s_sid.reserve(Sp), "alloc screen");
+    CHK(ws.s_nh.reserve(Sp), "alloc screen");
+    CHK(launch_screen_unpack(ws.s_keys.p, S, Sp, ws.s_sid.p, ws.s_nh.p, s), "screen unpack");
+    CHK(ws.s_X.reserve(Sp * ld), "alloc screen block");
+    CHK(fill_u32((uint32_t*)ws.s_X.p, 0u, Sp * ld / 2, s), "fill");
+    CHK(launch_screen_pack(sx->rows.rp.p, sx->rows.rc.p, ws.s_sid.p, S, head, ld, ws.s_X.p, s), "screen pack");
+    // tiles (I, J), I <= J, whose largest norm product reaches t
+    std::vector<float> nh((size_t)S);
+    CHK(hipMemcpyAsync(nh.data(), ws.s_nh.p, sizeof(float) * S, hipMemcpyDeviceToHost, s), "screen norms");
+    CHK(hipStreamSynchronize(s), "screen norms");
+    const int64_t T = Sp / kScreenTile;
+    std::vector<int32_t> tl;
+    for (int64_t I = 0; I < T; ++I) {
+      const float nI = nh[(size_t)(I * kScreenTile)];
+      for (int64_t J = I; J < T; ++J) {
+        if (nI * nh[(size_t)(J * kScreenTile)] * (1.0f + 0x1p-20f) < t) break;
+        tl.push_back((int32_t)I);
+        tl.push_back((int32_t)J);
+      }
+    }
+    ntiles = (int64_t)tl.size() / 2;
+    if (ntiles > 0) {
+      CHK(ws.s_tiles.reserve((int64_t)tl.size()), "alloc screen");
+      CHK(hipMemcpyAsync(ws.s_tiles.p, tl.data(), sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice, s),
+          "screen tiles");
+      CHK(ws.s_cand.reserve(std::max<int64_t>(1 << 16, 4 * S)), "alloc screen");
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        CHK(fill_u64((uint64_t*)ws.s_cnt.p, 0ull, 1, s), "fill");
+        ScreenArgs A;
+        A.X = ws.s_X.p;
+        A.ld = ld;
+        A.nh = ws.s_nh.p;
+        A.sid = ws.s_sid.p;
+        A.tiles = ws.s_tiles.p;
+        A.ntiles = ntiles;
+        A.t = t;
+        A.bj = bj;
+        A.out = ws.s_cand.p;
+        A.cap = ws.s_cand.n;
+        A.count = ws.s_cnt.p;
+        CHK(hipEventRecord(ws.ev[4], s), "event");
+        CHK(launch_screen_mfma(A, s), "screen kernel");
+        CHK(hipEventRecord(ws.ev[5], s), "event");
+        unsigned long long c = 0;
+        CHK(hipMemcpyAsync(&c, ws.s_cnt.p, sizeof(c), hipMemcpyDeviceToHost, s), "screen count");
+        CHK(hipStreamSynchronize(s), "screen kernel");
+        nc = (int64_t)c;
+        if (nc > ws.s_cand.n) {
+          CHK(ws.s_cand.alloc(nc + nc / 8 + 1024), "alloc screen");
+          continue;
+        }
+        float ms = 0.0f;
+        CHK(hipEventElapsedTime(&ms, ws.ev[4], ws.ev[5]), "event");
+        ws.last.ms_screen = ms;
+        break;
+      }
+      if (nc > ws.s_cand.n) {
+        set_error("screen candidate buffer kept overflowing");
+        return APSS_ENOMEM;
+      }
+    }
+  }
+
+  // sparse pass over the head-cut index, then the exact check of the screen's candidates
+  JoinPlan P;
+  if ((rc = plan_join(sx, ws, QuerySet{sx->rows.rp.p, sx->rows.rc.p, sx->rows.mw.p, n, sx->nnz,
+                                       sx->rows.rp_host.data()},
+                      1, t, nullptr, sx->rs.p, P)))
+    return rc;
+  if ((rc = ensure_pair_capacity(ws, cap_hint))) return rc;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    CHK(fill_u64((uint64_t*)ws.counters.p, 0ull, C_NUM, s), "fill");
+    CHK(hipEventRecord(ws.ev[1], s), "event");
+    if ((rc = launch_planned(ws, P))) return rc;
+    CHK(hipEventRecord(ws.ev[2], s), "event");
+    CHK(launch_screen_verify(ws.s_cand.p, nc, bj, sx->rows.rp.p, sx->rows.rc.p, head, t, ws.raw_key.p, ws.raw_sim.p,
+                             ws.raw_key.n, ws.counters.p, s),
+        "screen verify");
+    unsigned long long c[C_NUM];
+    CHK(hipMemcpyAsync(c, ws.counters.p, sizeof(c), hipMemcpyDeviceToHost, s), "read counters");
+    CHK(hipStreamSynchronize(s), "join");
+    const int64_t matches = (int64_t)c[C_MATCHES];
+    if (matches > ws.raw_key.n) {
+      if ((rc = ensure_pair_capacity(ws, matches + matches / 8 + 1024))) return rc;
+      ++ws.regrows;
+      continue;
+    }
+    const double ms_screen = ws.last.ms_screen;
+    take_counters(ws, c);
+    ws.last.ms_screen = ms_screen;
+    ws.last.screen_rows = S;
+    ws.last.screen_tiles = ntiles;
+    ws.last.screen_candidates = nc;
+    ws.last.screen_ld = ld;
+    float ms = 0.0f;
+    CHK(hipEventElapsedTime(&ms, ws.ev[1], ws.ev[2]), "event");
+    ws.last.ms_candidates = ms;
+    if ((rc = sort_pairs(ws, matches, 2 * bj))) return rc;
     *count = matches;
     return APSS_OK;
   }
@@ -613,6 +851,11 @@ QuerySet staged_queries(const RankRows& r) {
 // Pair capacity a self-join starts with (grows on overflow).
 int64_t join_cap_hint(const apss_index* ix) { return std::max<int64_t>(1 << 20, 16 * ix->n); }
 
+int self_join(apss_index* ix, float t, int64_t* cnt) {
+  if (ix->screen) return run_screen_join(ix, ix->ws, t, join_cap_hint(ix), cnt);
+  return run_join(ix, ix->ws, corpus_queries(ix), 1, t, nullptr, join_cap_hint(ix), cnt);
+}
+
 }  // namespace
 
 extern "C" {
@@ -626,6 +869,7 @@ void apss_default_opts(apss_opts* o) {
   o->variant = -1;
   o->head_dims = 0;
   o->range_rows = 0;
+  o->screen_dims = 0;
 }
 
 int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const float* val, int on_device,
@@ -660,6 +904,10 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
     set_error("range_rows must be >= 0");
     return APSS_EINVAL;
   }
+  if (o.screen_dims < 0 || o.screen_dims > kScreenMaxHead) {
+    set_error("screen_dims must be in [0, %d]", kScreenMaxHead);
+    return APSS_EINVAL;
+  }
   apss_index* ix = new (std::nothrow) apss_index();
   if (!ix) {
     set_error("host allocation failed");
@@ -682,6 +930,7 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
   }
   (void)hipGetDevice(&ix->device);
   int rc = build_impl(ix, row_ptr, col, val, on_device);
+  if (!rc && o.screen_dims > 0) rc = build_screen(ix, (int32_t)std::min<int64_t>(o.screen_dims, m));
   if (rc) {
     (void)hipStreamSynchronize(ix->ws.stream);
     apss_index_free(ix);
@@ -694,6 +943,7 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
 void apss_index_free(apss_index* idx) {
   if (!idx) return;
   (void)hipStreamSynchronize(idx->ws.stream);
+  apss_index_free(idx->screen);
   delete idx;
 }
 
@@ -706,7 +956,7 @@ int apss_join_device(apss_index* ix, float t, uint32_t* out_i, uint32_t* out_j, 
   int rc = check_t(ix, t);
   if (rc) return rc;
   int64_t cnt = 0;
-  if ((rc = run_join(ix, ix->ws, corpus_queries(ix), 1, t, nullptr, join_cap_hint(ix), &cnt))) return rc;
+  if ((rc = self_join(ix, t, &cnt))) return rc;
   return finish_device(ix->ws, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count);
 }
 
@@ -721,7 +971,7 @@ int apss_join(apss_index* ix, float t, apss_pairs* out) {
   int rc = check_t(ix, t);
   if (rc) return rc;
   int64_t cnt = 0;
-  if ((rc = run_join(ix, ix->ws, corpus_queries(ix), 1, t, nullptr, join_cap_hint(ix), &cnt))) return rc;
+  if ((rc = self_join(ix, t, &cnt))) return rc;
   return finish_host(ix->ws, cnt, ceil_log2((uint64_t)ix->n), out);
 }
 

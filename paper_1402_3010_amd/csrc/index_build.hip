@@ -5,7 +5,9 @@
 //  k_dim_keys / k_rank_from_sorted    density order: decreasing count, ties by id
 //  k_row_keys / k_unpack_rows         every row's components re-ordered densest first
 //  k_cutoff                           running bound b = sum x[d] maxweight_d(V) in double;
-//                                     the leading components with b < t are x'
+//                                     the leading components with b < t are x' (or, for
+//                                     the head-cut index of the screened join, the
+//                                     components of rank < head)
 //  k_count_indexed / k_emit_indexed   inverted lists of the indexed parts, by vector id
 //  k_block_offsets                    where each dense list enters each corpus block
 #include "apss_internal.h"
@@ -113,7 +115,7 @@ __global__ void k_unpack_rows(const uint64_t* __restrict__ keys, const uint32_t*
 // the running bound including it reaches t; with l2 the unindexed part also
 // ends once its own squared norm reaches t^2 (exact for float t).
 __global__ void k_cutoff(const int64_t* __restrict__ rp, const RComp* __restrict__ rc, const float* __restrict__ mw_r,
-                         int64_t n, float t, int l2, RowStat* __restrict__ rs, float* __restrict__ xmw,
+                         int64_t n, float t, int l2, int32_t head, RowStat* __restrict__ rs, float* __restrict__ xmw,
                          int64_t* __restrict__ nidx) {
   const double td = (double)t;
   const double t2 = td * td;
@@ -126,9 +128,16 @@ __global__ void k_cutoff(const int64_t* __restrict__ rp, const RComp* __restrict
     for (int32_t k = 0; k < len; ++k) {
       const RComp c = rc[a + k];
       const double w = (double)c.w;
-      b += w * (double)mw_r[c.r];
-      sq += w * w;
-      if (b >= td || (l2 && sq >= t2)) {
+      bool stop;
+      if (head > 0) {
+        stop = c.r >= head;  // head cut: the unindexed part is the head
+        sq += w * w;
+      } else {
+        b += w * (double)mw_r[c.r];
+        sq += w * w;
+        stop = b >= td || (l2 && sq >= t2);
+      }
+      if (stop) {
         cut = k;
         break;
       }
@@ -301,8 +310,8 @@ hipError_t launch_unpack_rows(const uint64_t* keys, const uint32_t* vals, int64_
 }
 
 hipError_t launch_cutoff(const int64_t* rp, const RComp* rc, const float* mw_r, int64_t n, float t, int l2,
-                         RowStat* rs, float* xmw, int64_t* nidx, hipStream_t s) {
-  LAUNCH(k_cutoff, n, rp, rc, mw_r, n, t, l2, rs, xmw, nidx);
+                         int32_t head, RowStat* rs, float* xmw, int64_t* nidx, hipStream_t s) {
+  LAUNCH(k_cutoff, n, rp, rc, mw_r, n, t, l2, head, rs, xmw, nidx);
   return hipSuccess;
 }
 

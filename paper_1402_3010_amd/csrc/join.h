@@ -22,6 +22,9 @@ struct JoinArgs {
   const int64_t* qrp;     // [nq+1]
   const RComp* qrc;       // [qnnz]
   const float* qmw;       // [nq] maxweight(q)
+  const RowStat* qrs;     // [nq] or NULL: when every corpus row's unindexed part is exactly its
+                          // components of rank < some head size, qrs[q].pnrm bounds the norm of
+                          // q's own head part (used in the L2 bound); NULL means 1
   const float* qt;        // [nq] per-query threshold, or NULL
   float t;                // threshold when qt is NULL
   int64_t nq;

@@ -19,8 +19,10 @@
 //     advance monotonically as the tile sweeps the blocks.
 //  2. filter each candidate (A > 0): size bound |y| maxweight(q) >= t,
 //     max-weight bound A + min(|y'|,|q|) maxweight(q) maxweight(y') >= t
-//     (the upperbound test of all-pairs-2), and the L2 bound A + ||y'|| >= t
-//     (Cauchy-Schwarz, ||q|| = 1); all with a small slack.
+//     (the upperbound test of all-pairs-2), and the L2 bound
+//     A + ||q_u|| ||y'|| >= t (Cauchy-Schwarz; q_u is q restricted to the
+//     dimensions that can be unindexed, so ||q_u|| <= 1, and it is q's head
+//     part when every row's unindexed part is its head); all with a small slack.
 //  3. verify survivors: s = A + dot(q, y') (one lane per survivor).
 //  4. rescore verified pairs over the full rows in float with compensated
 //     products and sums (Ogita, Rump and Oishi 2005, Dot2) in a fixed
@@ -29,6 +31,7 @@
 //     rescore.  Emitted pairs are compacted per wave (ballot + prefix).
 #include "apss_internal.h"
 #include "join.h"
+#include "rescore.h"
 
 namespace apss {
 
@@ -57,6 +60,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
 // segments at least this long are streamed by a whole wave
 constexpr int kLongSeg = 32;
 
+// list cursor of a staged component whose list has no entry in the work item's range
+constexpr uint32_t kDead = 0xFFFFFFFFu;
+
 // Values known to be equal across the wave, moved to scalar registers so that
 // loops and branches on them stay scalar.
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -64,12 +70,6 @@ __device__ __forceinline__ int64_t uni64(int64_t x) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-  s = __fadd_rn(a, b);
-  const float z = __fsub_rn(s, a);
-  e = __fadd_rn(__fsub_rn(a, __fsub_rn(s, z)), __fsub_rn(b, z));
 }
 
 // One dense-list segment of a (tile, block): list positions [pos, pos + len)
@@ -105,6 +105,7 @@ struct Smem {
   uint8_t cqi[C::QB];    // query slot of each staged component
   int64_t qoff[C::QT + 1];
   float qmw[C::QT];
+  float qpn[C::QT];  // bound on the query's part in the corpus rows' unindexed dimensions
   float qt[C::QT];
   int32_t qlen[C::QT];
   int32_t qhead[C::QT];
@@ -169,6 +170,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   if (tid <= qn) sm.qoff[tid] = a.qrp[q0 + tid];
   if (tid < QT) {
     sm.qmw[tid] = tid < qn ? a.qmw[q0 + tid] : 0.0f;
+    sm.qpn[tid] = (tid < qn && a.qrs) ? a.qrs[q0 + tid].pnrm : 1.0f;
     sm.qt[tid] = (tid < qn && a.qt) ? a.qt[q0 + tid] : a.t;
   }
   if (tid == 0) {
@@ -216,8 +218,10 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       const int qi = find_slot(qbase + k);
       if (c.r < RD) sm.qd[qi * RD + c.r] = c.w;
       uint32_t p0, ny = 0;
+      bool dead = false;  // no list entry in the item's corpus range
       if (c.r < a.H) {
         p0 = a.hoff[b_begin * (int64_t)a.H + c.r];
+        dead = a.hoff[b_end * (int64_t)a.H + c.r] == p0;
       } else {
         p0 = a.toff[R * (int64_t)a.m_tail + (c.r - a.H)];
         ny = (int64_t)p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
@@ -225,8 +229,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       if (staged) {
         sm.qrow[k] = c;
         sm.cqi[k] = (uint8_t)qi;
-        sm.cur[k] = make_uint2(p0, ny);
-        if (c.r < a.H) {
+        sm.cur[k] = make_uint2(dead ? kDead : p0, ny);
+        if (c.r < a.H && !dead) {
 #pragma unroll
           for (int j = 0; j < KMAX; ++j)
             if (k == (int64_t)j * NT + tid) hn[j] = a.hoff[(b_begin + 1) * (int64_t)a.H + c.r];
@@ -308,7 +312,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             pos = gcur[2 * k];
             ny = gcur[2 * k + 1];
           }
-          if (c.r < a.H) {
+          if (pos == kDead) {
+            // no entry of this list in the item's range
+          } else if (c.r < a.H) {
             uint32_t e;
             if (staged) {
               e = hn[j];
@@ -535,8 +541,29 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     // ------------------------------------------------------------ filter, verify, rescore
     auto drain = [&]() {
       const int ns = uni(sm.qcount < SQ ? sm.qcount : SQ);
-      // verify: one lane per survivor, s = A + dot(q, y'); y' is the first
-      // cut components of the row, densest dimension first
+      // verify s = A + dot(q, y'); y' is the first cut components of the row,
+      // densest dimension first.  Few survivors: one wave per survivor, lanes
+      // over y' (short latency chain); many: one lane per survivor.
+      if (ns <= 4 * NW) {
+        for (int e = wave; e < ns; e += NW) {
+          const uint4 it = sm.sq[e];
+          const int qi = (int)(it.x >> 16);
+          uint32_t cut = it.w & 0xFFFFu;
+          if ((it.w >> 16) == 0xFFFFu) cut = (uint32_t)a.rs[blk0 + (it.x & 0xFFFFu)].cut;
+          float part = 0.0f;
+          for (uint32_t k = (uint32_t)lane; k < cut; k += 64) {
+            const RComp c = a.rc[it.z + k];
+            part += qlookup(qi, c.r) * c.w;
+          }
+#pragma unroll
+          for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+          const float sc = (float)it.y * kInvFix + part;
+          if (lane == 0) {
+            if (sc >= sm.qt[qi] - kSlack) ++c_ver;
+            else sm.sq[e].y = 0u;
+          }
+        }
+      } else
       for (int e = tid; e < ns; e += NT) {
         const uint4 it = sm.sq[e];
         const int qi = (int)(it.x >> 16);
@@ -568,45 +595,13 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           const int64_t ys = it.z;
           int ylen = (int)(it.w >> 16);
           if (ylen == 0xFFFF) ylen = (int)(a.rp[y + 1] - a.rp[y]);
-          float hi = 0.0f, lo = 0.0f;
-          for (int k = lane; k < ylen; k += 64) {
-            const RComp c = a.rc[ys + k];
-            const float qv = qlookup(qi, c.r);
-            const float p = __fmul_rn(qv, c.w);
-            const float ep = __fmaf_rn(qv, c.w, -p);
-            float s2, es;
-            two_sum(hi, p, s2, es);
-            hi = s2;
-            lo = __fadd_rn(lo, __fadd_rn(es, ep));
-          }
-#pragma unroll
-          for (int o = 32; o >= 1; o >>= 1) {
-            const float h2 = __shfl_xor(hi, o, 64);
-            const float l2 = __shfl_xor(lo, o, 64);
-            float s2, e2;
-            two_sum(hi, h2, s2, e2);
-            hi = s2;
-            lo = __fadd_rn(__fadd_rn(lo, l2), e2);
-          }
-          const float s32 = __fadd_rn(hi, lo);
-          const float tq = sm.qt[qi];
-          bool keep;
+          const RComp* yrow = a.rc + ys;
+          auto look = [&](int32_t r) { return qlookup(qi, r); };
+          const float s32 = wave_dot2(yrow, ylen, lane, look);
           float sim;
-          if (fabsf(s32 - tq) <= kBand) {
-            double d = 0.0;
-            for (int k = lane; k < ylen; k += 64) {
-              const RComp c = a.rc[ys + k];
-              d += (double)qlookup(qi, c.r) * (double)c.w;
-            }
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
-            keep = d >= (double)tq;
-            sim = (float)d;
-            if (lane == 0) ++c_band;
-          } else {
-            keep = s32 >= tq;
-            sim = s32;
-          }
+          bool banded;
+          const bool keep = wave_decide(yrow, ylen, lane, look, s32, sm.qt[qi], &sim, &banded);
+          if (banded && lane == 0) ++c_band;
           if (keep && lane == 0) {
             const uint64_t qid = (uint64_t)(q0 + qi);
             const uint64_t key = a.triangle ? (((uint64_t)y << a.bj) | qid) : ((qid << a.bj) | (uint64_t)y);
@@ -652,7 +647,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             const float qm = sm.qmw[qi];
             const int ql = sm.qlen[qi];
             const float mn = (float)(st.cut < ql ? st.cut : ql);
-            want = ((float)ylen * qm >= thr) && (A + mn * qm * st.pmw >= thr) && (A + st.pnrm >= thr);
+            want = ((float)ylen * qm >= thr) && (A + mn * qm * st.pmw >= thr) && (A + sm.qpn[qi] * st.pnrm >= thr);
             ++c_cand;
           }
           const uint64_t wm = __ballot(want);

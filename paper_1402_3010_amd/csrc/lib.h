@@ -82,16 +82,23 @@ struct Workspace {
   DBuf<float> qt;
   DBuf<uint32_t> err;
   DBuf<unsigned long long> bad;
+  // head screen of the screened join
+  DBuf<uint64_t> s_keys, s_cand;
+  DBuf<unsigned long long> s_cnt;
+  DBuf<int32_t> s_sid, s_tiles;
+  DBuf<float> s_nh;
+  DBuf<uint16_t> s_X;
   apss_stats last;
   int64_t regrows = 0;  // joins rerun because the pair buffer was too small
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   ~Workspace() {
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 6; ++e)
       if (ev[e]) (void)hipEventDestroy(ev[e]);
   }
   int64_t bytes() const {
     return ss.bytes() + tstart.bytes() + qcum.bytes() + qctr.bytes() + wg_cur.bytes() + counters.bytes() +
-           raw_key.bytes() + raw_sim.bytes() + qt.bytes();
+           raw_key.bytes() + raw_sim.bytes() + qt.bytes() + s_keys.bytes() + s_cand.bytes() + s_sid.bytes() +
+           s_tiles.bytes() + s_nh.bytes() + s_X.bytes();
   }
 };
 
@@ -105,6 +112,8 @@ struct apss_index {
   int32_t H = 0;
   int variant = 1;          // tile variant of the join kernel
   int64_t range_rows = 0;   // corpus rows per work-item range
+  int32_t head_cut = 0;     // > 0: the unindexed part of every row is its components of rank < head_cut
+  apss_index* screen = nullptr;  // head-cut index over the same rows (screened join), owned
   apss::RankRows rows;  // corpus rows in rank space (densest dimension first)
   apss::DBuf<apss::RowStat> rs;
   apss::DBuf<int32_t> rank, inv;
@@ -148,6 +157,8 @@ int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_ro
 // *count.  cap_hint: pair capacity to start with (grown and rerun on overflow).
 int run_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, float t, const float* qt_dev,
              int64_t cap_hint, int64_t* count);
+// Screened self-join of an index built with screen_dims > 0 (ix->screen set).
+int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, int64_t* count);
 // Unpack the sorted raw pairs into device arrays / library-owned host arrays.
 int finish_device(Workspace& ws, int64_t cnt, int bj, uint32_t* out_i, uint32_t* out_j, float* out_sim,
                   int64_t capacity, int64_t* count);

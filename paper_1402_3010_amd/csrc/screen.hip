@@ -1,0 +1,299 @@
+// Head screen of the screened self-join.
+//
+// Partial indexing (Section 3.2.2) leaves the densest dimensions out of
+// the inverted lists, and the paper notes that this splits the work into a
+// dense and a sparse phase, the dense one suited to brute force.  The
+// screened join makes that split explicit with a fixed head: the `head`
+// densest dimensions.  A pair (x, y) has sim = H + T, H over the head and T
+// over the tail.
+//
+//  * Pairs with T > 0 share a tail dimension; the sparse pass (the join
+//    kernel over an index whose unindexed part of every row is its head)
+//    finds and decides all of them.
+//  * Pairs with T = 0 have sim = H <= ||x_h|| ||y_h||, so both rows have
+//    head norm >= t.  Those rows are gathered (sorted by decreasing head
+//    norm), their head parts packed as a dense bf16 block, and H~ is formed
+//    for every pair of them whose norm product reaches t by bf16 MFMA with
+//    float accumulation.  A pair is a candidate when
+//    H~ >= t - kScreenMargin ||x_h|| ||y_h|| - kScreenEps, which no pair with
+//    H >= t can miss; candidates that share no tail dimension are rescored
+//    exactly and decided like every other pair.
+//
+// The two sets are disjoint and their union is every pair with sim >= t.
+#include "apss_internal.h"
+#include "rescore.h"
+#include "screen.h"
+
+namespace apss {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+#define LAUNCH1D(kern, nthreads, ...)                                                       \
+  do {                                                                                      \
+    const int64_t nt__ = (nthreads);                                                        \
+    if (nt__ > 0) {                                                                         \
+      int64_t g__ = (nt__ + 255) / 256;                                                     \
+      if (g__ > 65536) g__ = 65536;                                                         \
+      hipLaunchKernelGGL(kern, dim3((unsigned)g__), dim3(256), 0, s, __VA_ARGS__);          \
+      const hipError_t e__ = hipGetLastError();                                             \
+      if (e__ != hipSuccess) return e__;                                                    \
+    }                                                                                       \
+  } while (0)
+
+__global__ void k_screen_select(const RowStat* __restrict__ rs, int64_t n, float t, uint64_t* __restrict__ keys,
+                                unsigned long long* __restrict__ count) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const float nh = rs[r].pnrm;
+    if (nh >= t) {
+      const unsigned long long k = atomicAdd(count, 1ull);
+      keys[k] = ((uint64_t)(0xFFFFFFFFu - __float_as_uint(nh)) << 32) | (uint64_t)r;
+    }
+  }
+}
+
+__global__ void k_screen_unpack(const uint64_t* __restrict__ keys, int64_t S, int64_t Sp, int32_t* __restrict__ sid,
+                                float* __restrict__ nh) {
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < Sp; a += (int64_t)gridDim.x * blockDim.x) {
+    if (a < S) {
+      const uint64_t k = keys[a];
+      sid[a] = (int32_t)(uint32_t)k;
+      nh[a] = __uint_as_float(0xFFFFFFFFu - (uint32_t)(k >> 32));
+    } else {
+      sid[a] = -1;
+      nh[a] = 0.0f;
+    }
+  }
+}
+
+// float -> bf16 bits, round to nearest even (weights are finite and positive)
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void k_screen_pack(const int64_t* __restrict__ rp, const RComp* __restrict__ rc,
+                              const int32_t* __restrict__ sid, int64_t S, int32_t head, int32_t ld,
+                              uint16_t* __restrict__ X) {
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < S; a += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = sid[a];
+    const int64_t b = rp[r], e = rp[r + 1];
+    uint16_t* row = X + a * (int64_t)ld;
+    // rank-space rows are in rank order: the head is a prefix
+    for (int64_t k = b; k < e; ++k) {
+      const RComp c = rc[k];
+      if (c.r >= head) break;
+      row[c.r] = bf16_rne(c.w);
+    }
+  }
+}
+
+// One workgroup (4 waves) per 128 x 128 output tile (I, J) of the packed
+// rows; wave w owns the 64 x 64 quarter (w / 2, w % 2) as 2 x 2 MFMA blocks
+// of 32 x 32 (v_mfma_f32_32x32x16_bf16, float accumulation).  Operands move
+// through LDS in K steps of 64, double-buffered via registers.  Lane l of a
+// 32 x 32 x 16 MFMA holds operand row (l % 32), k = 8 (l / 32) .. + 7; result
+// element r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+constexpr int kLda = kScreenK + 8;  // LDS row pitch in bf16 (16 bytes of padding)
+
+__global__ __launch_bounds__(256) void k_screen_mfma(ScreenArgs a, int64_t chunk) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][kScreenTile * kLda];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kScreenTile * kLda];
+  // the workgroups of one XCD (round-robin over blockIdx) take one
+  // contiguous chunk of the tile list, which is ordered by I
+  const int64_t ti = (int64_t)(blockIdx.x & 7u) * chunk + (int64_t)(blockIdx.x >> 3);
+  if (ti >= a.ntiles) return;
+  const int I = a.tiles[2 * ti], J = a.tiles[2 * ti + 1];
+  const int64_t a0 = (int64_t)I * kScreenTile, b0 = (int64_t)J * kScreenTile;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int nkb = a.ld / kScreenK;
+
+  uint4 ra[4], rb[4];
+  auto gload = [&](int kb) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = tid + 256 * u;
+      const int row = c >> 3, col = (c & 7) * 8;
+      ra[u] = *reinterpret_cast<const uint4*>(a.X + (a0 + row) * a.ld + kb * kScreenK + col);
+      rb[u] = *reinterpret_cast<const uint4*>(a.X + (b0 + row) * a.ld + kb * kScreenK + col);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = tid + 256 * u;
+      const int row = c >> 3, col = (c & 7) * 8;
+      *reinterpret_cast<uint4*>(&As[buf][row * kLda + col]) = ra[u];
+      *reinterpret_cast<uint4*>(&Bs[buf][row * kLda + col]) = rb[u];
+    }
+  };
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int frow = lane & 31, fk = 8 * (lane >> 5);
+  for (int kb = 0; kb < nkb; ++kb) {
+    const int cur = kb & 1;
+    if (kb + 1 < nkb) gload(kb + 1);
+#pragma unroll
+    for (int kk = 0; kk < kScreenK / 16; ++kk) {
+      bf16x8 fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        fa[i] = *reinterpret_cast<const bf16x8*>(&As[cur][(wr + 32 * i + frow) * kLda + 16 * kk + fk]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        fb[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][(wc + 32 * j + frow) * kLda + 16 * kk + fk]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (kb + 1 < nkb) lstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: threshold test and compaction by wave ballot
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int64_t b = b0 + wc + 32 * j + (lane & 31);
+    const float nb = a.nh[b];
+    const int32_t ib = a.sid[b];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t ar = a0 + wr + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const float na = a.nh[ar];
+        const float p = na * nb;
+        const bool want = (I < J || ar < b) && p * (1.0f + 0x1p-20f) >= a.t &&
+                          acc[i][j][r] >= a.t - kScreenMargin * p - kScreenEps;
+        const uint64_t m = __ballot(want);
+        if (m) {
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(a.count, (unsigned long long)__popcll(m));
+          base = __shfl(base, 0);
+          if (want) {
+            const unsigned long long k = base + (unsigned long long)__popcll(m & lt);
+            if ((int64_t)k < a.cap) {
+              const uint32_t ia = (uint32_t)a.sid[ar];
+              const uint32_t lo = ia < (uint32_t)ib ? ia : (uint32_t)ib;
+              const uint32_t hi = ia < (uint32_t)ib ? (uint32_t)ib : ia;
+              a.out[k] = ((uint64_t)lo << a.bj) | (uint64_t)hi;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// q's weight in rank r by binary search of its rank-ordered row (0 if absent)
+__device__ __forceinline__ float row_lookup(const RComp* __restrict__ q, int qlen, int32_t r) {
+  int lo = 0, hi = qlen;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (q[mid].r < r) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < qlen && q[lo].r == r) ? q[lo].w : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_screen_verify(const uint64_t* __restrict__ cand, int64_t nc, int bj,
+                                                       const int64_t* __restrict__ rp, const RComp* __restrict__ rc,
+                                                       int32_t head, float t, uint64_t* __restrict__ out_key,
+                                                       float* __restrict__ out_sim, int64_t cap,
+                                                       unsigned long long* __restrict__ counters) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const uint64_t jmask = (1ull << bj) - 1ull;
+  for (int64_t p = wv; p < nc; p += nw) {
+    const uint64_t key = cand[p];
+    const int64_t i = (int64_t)(key >> bj), j = (int64_t)(key & jmask);
+    // y = the smaller id, q = the larger: the orientation of the join kernel
+    const int64_t ys = rp[i], qs = rp[j];
+    const int ylen = (int)(rp[i + 1] - ys), qlen = (int)(rp[j + 1] - qs);
+    const RComp* yrow = rc + ys;
+    const RComp* qrow = rc + qs;
+    auto look = [&](int32_t r) { return row_lookup(qrow, qlen, r); };
+    bool tail = false;
+    for (int k = lane; k < ylen; k += 64) {
+      const RComp c = yrow[k];
+      if (c.r >= head && look(c.r) != 0.0f) tail = true;
+    }
+    if (__ballot(tail)) continue;  // shares a tail dimension: decided by the sparse pass
+    const float s32 = wave_dot2(yrow, ylen, lane, look);
+    float sim;
+    bool banded;
+    const bool keep = wave_decide(yrow, ylen, lane, look, s32, t, &sim, &banded);
+    if (lane == 0) {
+      if (banded) atomicAdd(&counters[C_BAND], 1ull);
+      if (keep) {
+        const unsigned long long k = atomicAdd(&counters[C_MATCHES], 1ull);
+        if ((int64_t)k < cap) {
+          out_key[k] = key;
+          out_sim[k] = sim;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_screen_select(const RowStat* rs, int64_t n, float t, uint64_t* keys, unsigned long long* count,
+                                hipStream_t s) {
+  LAUNCH1D(k_screen_select, n, rs, n, t, keys, count);
+  return hipSuccess;
+}
+
+hipError_t launch_screen_unpack(const uint64_t* keys, int64_t S, int64_t Sp, int32_t* sid, float* nh, hipStream_t s) {
+  LAUNCH1D(k_screen_unpack, Sp, keys, S, Sp, sid, nh);
+  return hipSuccess;
+}
+
+hipError_t launch_screen_pack(const int64_t* rp, const RComp* rc, const int32_t* sid, int64_t S, int32_t head,
+                              int32_t ld, uint16_t* X, hipStream_t s) {
+  LAUNCH1D(k_screen_pack, S, rp, rc, sid, S, head, ld, X);
+  return hipSuccess;
+}
+
+hipError_t launch_screen_mfma(const ScreenArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  if (!a.X || !a.nh || !a.sid || !a.tiles || !a.out || !a.count || a.ld <= 0 || a.ld % kScreenK)
+    return hipErrorInvalidValue;
+  const int64_t chunk = (a.ntiles + 7) / 8;
+  const int64_t grid = 8 * chunk;
+  if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_screen_mfma, dim3((unsigned)grid), dim3(256), 0, s, a, chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen_verify(const uint64_t* cand, int64_t nc, int bj, const int64_t* rp, const RComp* rc,
+                                int32_t head, float t, uint64_t* out_key, float* out_sim, int64_t cap,
+                                unsigned long long* counters, hipStream_t s) {
+  if (nc <= 0) return hipSuccess;
+  if (!cand || !rp || !rc || !out_key || !out_sim || !counters) return hipErrorInvalidValue;
+  int64_t g = (nc + 3) / 4;  // 4 waves per workgroup, one pair per wave
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_screen_verify, dim3((unsigned)g), dim3(256), 0, s, cand, nc, bj, rp, rc, head, t, out_key,
+                     out_sim, cap, counters);
+  return hipGetLastError();
+}
+
+}  // namespace apss
