@@ -70,6 +70,10 @@ typedef struct {
   int32_t screen_dims;   /* > 0 (at most 8192): apss_join / apss_join_device use the screened join
                             with this many densest dimensions as the dense head (bf16 MFMA screen
                             plus a sparse pass over the rest); 0 (default): plain join only */
+  int32_t graph;         /* 1: apss_join_device (plain join) captures its launch sequence in a HIP
+                            graph and replays it on later calls with the same t and output
+                            buffers (one launch, one synchronisation per call); the graph's
+                            stats report its whole device time as ms_candidates.  0: default */
   int32_t reserved[8];
 } apss_opts;
 
@@ -157,6 +161,30 @@ int apss_index_sizes(const apss_index* idx, int64_t* n, int64_t* m, int64_t* nnz
 
 const char* apss_strerror(int code);
 const char* apss_last_error(void);
+
+/* ---- Autotuning of the self-join ----
+ * Times the join kernel at threshold t on this index under every compiled
+ * tile variant (queries per tile x corpus rows per LDS accumulator block)
+ * and several corpus-range widths of the persistent kernel's work items,
+ * and keeps the fastest for later joins on the index (for an index built
+ * with screen_dims > 0: the sparse pass of the screened join).  budget_ms > 0
+ * stops trying further configurations once that much host time has passed
+ * (the current configuration is always timed first).  With cache_path, the
+ * choice is first looked up in that JSON file under a key made of the device
+ * architecture, the join kind and the workload class (n, m and nnz per row to
+ * the nearest power of two, t to two decimals), and stored there after
+ * tuning.  The index must not be in use by another call or a server. */
+typedef struct {
+  int32_t variant;             /* chosen tile variant */
+  int32_t range_rows;          /* chosen corpus rows per work item */
+  double ms;                   /* its join kernel time (from the cache if from_cache) */
+  int32_t from_cache;          /* 1: taken from the cache file without timing */
+  int32_t tried;               /* configurations timed */
+  int32_t cache_write_failed;  /* 1: the cache file could not be written */
+  int32_t reserved[3];
+} apss_tune_result;
+
+int apss_autotune(apss_index* idx, float t, double budget_ms, const char* cache_path, apss_tune_result* out);
 
 /* ---- Serving: continuous batching of query requests on a resident index ----
  *

@@ -40,7 +40,8 @@ class ApssError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("stream", ctypes.c_void_p), ("query_safe", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("head_dims", ctypes.c_int32), ("range_rows", ctypes.c_int32),
-                ("screen_dims", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("screen_dims", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class Pairs(ctypes.Structure):
@@ -75,6 +76,12 @@ class ServerCounters(ctypes.Structure):
         (k, ctypes.c_int64) for k in ("submitted", "rejected_busy", "completed", "failed", "queued", "batches",
                                       "queries", "overlapped_batches", "peak_running", "regrows", "reserved_bytes",
                                       "peak_reserved_bytes")] + [("device_bytes", ctypes.c_int64 * SERVER_MAX_SLOTS)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("range_rows", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("from_cache", ctypes.c_int32), ("tried", ctypes.c_int32), ("cache_write_failed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 _LIB = None
@@ -123,6 +130,8 @@ def load(path: str = LIB_PATH):
     lib.apss_strerror.restype = ctypes.c_char_p
     lib.apss_last_error.argtypes = []
     lib.apss_last_error.restype = ctypes.c_char_p
+    lib.apss_autotune.argtypes = [P, f32, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
+    lib.apss_autotune.restype = ctypes.c_int
     lib.apss_server_default_opts.argtypes = [ctypes.POINTER(ServerOpts)]
     lib.apss_server_default_opts.restype = None
     lib.apss_server_create.argtypes = [P, ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]
@@ -143,7 +152,7 @@ def load(path: str = LIB_PATH):
 
 EXPORTED = ("apss_default_opts", "apss_build_index", "apss_index_free", "apss_join_device", "apss_join",
             "apss_query", "apss_query_device", "apss_pairs_free", "apss_last_stats", "apss_index_export",
-            "apss_index_sizes", "apss_strerror", "apss_last_error", "apss_server_default_opts",
+            "apss_index_sizes", "apss_strerror", "apss_last_error", "apss_autotune", "apss_server_default_opts",
             "apss_server_create", "apss_submit", "apss_poll", "apss_server_pause", "apss_server_stats",
             "apss_server_destroy")
 
@@ -190,7 +199,7 @@ def current_stream_handle() -> Optional[int]:
 
 
 def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, variant: int = -1,
-                 range_rows: int = 0, screen_dims: int = 0) -> Opts:
+                 range_rows: int = 0, screen_dims: int = 0, graph: bool = False) -> Opts:
     o = Opts()
     load().apss_default_opts(ctypes.byref(o))
     o.stream = stream
@@ -199,6 +208,7 @@ def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, varia
     o.variant = variant
     o.range_rows = range_rows
     o.screen_dims = screen_dims
+    o.graph = 1 if graph else 0
     return o
 
 
@@ -288,6 +298,12 @@ def last_stats(h: int) -> dict:
     return {k: getattr(s, k) for k, _ in Stats._fields_}
 
 
+def autotune(h: int, t: float, budget_ms: float = 0.0, cache: Optional[str] = None) -> dict:
+    r = TuneResult()
+    _check(load().apss_autotune(h, float(t), float(budget_ms), cache.encode() if cache else None, ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in TuneResult._fields_ if k != "reserved"}
+
+
 def index_sizes(h: int) -> dict:
     v = [ctypes.c_int64() for _ in range(4)]
     _check(load().apss_index_sizes(h, *[ctypes.byref(x) for x in v]))
@@ -312,7 +328,8 @@ class Index:
 
     @classmethod
     def build(cls, V, t_build: float, stream=None, query_safe: bool = True, head_dims: int = 0,
-              on_device: bool = False, variant: int = -1, range_rows: int = 0, screen_dims: int = 0) -> "Index":
+              on_device: bool = False, variant: int = -1, range_rows: int = 0, screen_dims: int = 0,
+              graph: bool = False) -> "Index":
         """V: object with n, m, row_ptr, col, val (numpy), or a tuple (n, m, row_ptr, col, val) of tensors."""
         if isinstance(V, tuple):
             n, m, rp, col, val = V
@@ -326,7 +343,7 @@ class Index:
         if stream is None:
             stream = current_stream_handle()
         h = build_index(n, m, rp, col, val, t_build, default_opts(stream, query_safe, head_dims, variant, range_rows,
-                                                                      screen_dims))
+                                                                      screen_dims, graph))
         return cls(h, int(n), int(m))
 
     def join(self, t: float):
@@ -343,6 +360,10 @@ class Index:
 
     def stats(self) -> dict:
         return last_stats(self.handle)
+
+    def autotune(self, t: float, budget_ms: float = 0.0, cache: Optional[str] = None) -> dict:
+        """apss_autotune: pick the tile variant and range width for joins at t (see the header)."""
+        return autotune(self.handle, t, budget_ms, cache)
 
     def export(self):
         return index_export(self.handle)

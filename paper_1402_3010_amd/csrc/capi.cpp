@@ -534,7 +534,10 @@ void take_counters(Workspace& ws, const unsigned long long* c) {
   ws.last.matches = (int64_t)c[C_MATCHES];
 }
 
-int start_call(Workspace& ws) {
+// Every call on a workspace starts here.  Any call other than a graph
+// replay may rewrite buffers a captured graph reads, so it drops the graph.
+int start_call(Workspace& ws, bool keep_graph = false) {
+  if (!keep_graph) ws.graph.reset();
   memset(&ws.last, 0, sizeof(ws.last));
   for (int e = 0; e < 6; ++e)
     if (!ws.ev[e]) CHK(hipEventCreateWithFlags(&ws.ev[e], hipEventDefault), "event");
@@ -717,6 +720,108 @@ int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, in
   return APSS_ENOMEM;
 }
 
+}  // namespace apss
+
+namespace {
+
+std::vector<const void*> graph_buffers(const apss_index* ix, const Workspace& ws) {
+  return {ws.tstart.p, ws.qcum.p, ws.qctr.p, ws.counters.p, ws.wg_cur.p, ws.raw_key.p, ws.raw_sim.p, ws.ss.k2.p,
+          ws.ss.v32b.p, ws.ss.hist.p, ws.ss.scan.p, ix->toff.p, ix->hoff[0].p, ix->hoff[1].p,
+          (const void*)(intptr_t)ix->variant, (const void*)(intptr_t)ix->range_rows};
+}
+
+// Capture the launch sequence of the self-join that just ran (count pairs).
+int capture_join_graph(apss_index* ix, float t, uint32_t* out_i, uint32_t* out_j, float* out_sim, int64_t capacity,
+                       int64_t cnt) {
+  Workspace& ws = ix->ws;
+  JoinGraph& g = ws.graph;
+  hipStream_t s = ws.stream;
+  g.reset();
+  if (!s) return APSS_OK;  // the legacy default stream cannot be captured
+  if (!g.hctr) CHK(hipHostMalloc((void**)&g.hctr, sizeof(unsigned long long) * C_NUM, hipHostMallocDefault),
+                   "pinned counters");
+  JoinPlan P;
+  int rc = plan_join(ix, ws, QuerySet{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz,
+                                      ix->rows.rp_host.data()},
+                     1, t, nullptr, nullptr, P);
+  if (rc) return rc;
+  CHK(hipStreamSynchronize(s), "graph capture");
+  CHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
+  auto body = [&]() -> int {
+    CHK(fill_u64((uint64_t*)ws.counters.p, 0ull, C_NUM, s), "fill");
+    int r = launch_planned(ws, P);
+    if (r) return r;
+    CHK(hipMemcpyAsync(g.hctr, ws.counters.p, sizeof(unsigned long long) * C_NUM, hipMemcpyDeviceToHost, s),
+        "read counters");
+    if ((r = sort_pairs(ws, cnt, P.bi + P.bj))) return r;
+    CHK(launch_unpack_pairs(ws.raw_key.p, ws.raw_sim.p, cnt, P.bj, out_i, out_j, out_sim, s), "unpack");
+    return APSS_OK;
+  };
+  rc = body();
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(s, &graph);
+  if (!rc && ee != hipSuccess) rc = dev_err(ee, "graph capture");
+  if (!rc) {
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      g.exec = nullptr;
+      rc = dev_err(ei, "graph instantiate");
+    }
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  if (rc) return rc;
+  g.t = t;
+  g.out[0] = out_i;
+  g.out[1] = out_j;
+  g.out[2] = out_sim;
+  g.capacity = capacity;
+  g.count = cnt;
+  g.baked = graph_buffers(ix, ws);
+  return APSS_OK;
+}
+
+// apss_join_device with graph replay (plain self-join).
+int graph_join(apss_index* ix, float t, uint32_t* out_i, uint32_t* out_j, float* out_sim, int64_t capacity,
+               int64_t* count) {
+  Workspace& ws = ix->ws;
+  JoinGraph& g = ws.graph;
+  hipStream_t s = ws.stream;
+  int rc;
+  if (g.exec && g.t == t && g.out[0] == out_i && g.out[1] == out_j && g.out[2] == out_sim &&
+      g.capacity == capacity && g.baked == graph_buffers(ix, ws)) {
+    if ((rc = start_call(ws, true))) return rc;
+    CHK(hipEventRecord(ws.ev[1], s), "event");
+    CHK(hipGraphLaunch(g.exec, s), "graph launch");
+    CHK(hipEventRecord(ws.ev[2], s), "event");
+    CHK(hipStreamSynchronize(s), "graph launch");
+    if ((int64_t)g.hctr[C_MATCHES] == g.count) {
+      take_counters(ws, g.hctr);
+      float ms = 0.0f;
+      CHK(hipEventElapsedTime(&ms, ws.ev[1], ws.ev[2]), "event");
+      ws.last.ms_candidates = ms;
+      CHK(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[2]), "event");
+      ws.last.ms_total = ms;
+      *count = g.count;
+      return APSS_OK;
+    }
+    g.reset();  // cannot happen for a deterministic join; recompute eagerly
+  }
+  int64_t cnt = 0;
+  if ((rc = run_join(ix, ws, QuerySet{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz,
+                                      ix->rows.rp_host.data()},
+                     1, t, nullptr, std::max<int64_t>(1 << 20, 16 * ix->n), &cnt)))
+    return rc;
+  if ((rc = finish_device(ws, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count))) return rc;
+  const apss_stats keep = ws.last;
+  rc = capture_join_graph(ix, t, out_i, out_j, out_sim, capacity, cnt);
+  ws.last = keep;
+  return rc;
+}
+
+}  // namespace
+
+namespace apss {
+
 int check_t(const apss_index* ix, float t) {
   if (!(t > 0.0f && t <= 1.0f)) {
     set_error("threshold %g outside (0, 1]", (double)t);
@@ -786,6 +891,7 @@ int finish_host(Workspace& ws, int64_t cnt, int bj, apss_pairs* out) {
 int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col,
                   const float* q_val, int on_device, const float* t_per_row, float t, RankRows& rows) {
   hipStream_t s = ws.stream;
+  ws.graph.reset();  // the staging reuses buffers a captured join graph reads
   if (!ix->opts.query_safe) {
     set_error("index was built with query_safe = 0; external queries need the L2 cutoff clause");
     return APSS_EINVAL;
@@ -870,6 +976,7 @@ void apss_default_opts(apss_opts* o) {
   o->head_dims = 0;
   o->range_rows = 0;
   o->screen_dims = 0;
+  o->graph = 0;
 }
 
 int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const float* val, int on_device,
@@ -955,6 +1062,7 @@ int apss_join_device(apss_index* ix, float t, uint32_t* out_i, uint32_t* out_j, 
   }
   int rc = check_t(ix, t);
   if (rc) return rc;
+  if (ix->opts.graph && !ix->screen && ix->n > 0) return graph_join(ix, t, out_i, out_j, out_sim, capacity, count);
   int64_t cnt = 0;
   if ((rc = self_join(ix, t, &cnt))) return rc;
   return finish_device(ix->ws, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count);

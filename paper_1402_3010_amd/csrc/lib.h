@@ -66,6 +66,27 @@ struct SortScratch {
   }
 };
 
+// A captured launch sequence of a self-join (fills, join kernel, counter
+// read-back, pair sort, unpack into the caller's buffers), replayed while
+// the threshold, the outputs and every buffer it names stay the same.
+struct JoinGraph {
+  hipGraphExec_t exec = nullptr;
+  float t = 0.0f;
+  const void* out[3] = {nullptr, nullptr, nullptr};
+  int64_t capacity = 0;
+  int64_t count = 0;
+  std::vector<const void*> baked;     // device buffers the graph uses
+  unsigned long long* hctr = nullptr;  // pinned copy of the counters
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+  ~JoinGraph() {
+    reset();
+    if (hctr) (void)hipHostFree(hctr);
+  }
+};
+
 // Everything one join or query call needs besides the index: its stream,
 // scratch, raw output and timing.  The index has one for apss_join and
 // apss_query; every slot of a server has its own, so calls on different
@@ -88,6 +109,7 @@ struct Workspace {
   DBuf<int32_t> s_sid, s_tiles;
   DBuf<float> s_nh;
   DBuf<uint16_t> s_X;
+  JoinGraph graph;
   apss_stats last;
   int64_t regrows = 0;  // joins rerun because the pair buffer was too small
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

@@ -78,8 +78,9 @@ int main(void) {
   printf("apss_server_opts %zu\n", sizeof(apss_server_opts));
   printf("apss_request_info %zu\n", sizeof(apss_request_info));
   printf("apss_server_counters %zu\n", sizeof(apss_server_counters));
+  printf("apss_tune_result %zu\n", sizeof(apss_tune_result));
   F(apss_opts, stream) F(apss_opts, query_safe) F(apss_opts, variant) F(apss_opts, head_dims)
-  F(apss_opts, range_rows) F(apss_opts, screen_dims) F(apss_opts, reserved)
+  F(apss_opts, range_rows) F(apss_opts, screen_dims) F(apss_opts, graph) F(apss_opts, reserved)
   F(apss_server_opts, slots) F(apss_server_opts, max_batch_queries) F(apss_server_opts, memory_budget)
   F(apss_server_opts, pairs_per_query) F(apss_server_opts, max_pending) F(apss_server_opts, reserved)
   F(apss_request_info, latency_ms) F(apss_request_info, batch) F(apss_request_info, batch_requests)
@@ -88,6 +89,7 @@ int main(void) {
   F(apss_server_counters, device_bytes)
   F(apss_stats, ms_candidates) F(apss_stats, ms_total) F(apss_stats, screen_rows) F(apss_stats, screen_ld)
   F(apss_stats, ms_screen)
+  F(apss_tune_result, ms) F(apss_tune_result, from_cache) F(apss_tune_result, cache_write_failed)
   return 0;
 }
 """
@@ -105,7 +107,7 @@ def test_struct_layouts_match_header(tmp_path):
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     mirrors = {"apss_opts": apss.Opts, "apss_pairs": apss.Pairs, "apss_stats": apss.Stats,
                "apss_server_opts": apss.ServerOpts, "apss_request_info": apss.RequestInfo,
-               "apss_server_counters": apss.ServerCounters}
+               "apss_server_counters": apss.ServerCounters, "apss_tune_result": apss.TuneResult}
     checked = 0
     for line in filter(None, out):
         parts = line.split()
