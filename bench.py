@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0  # dense bf16 MFMA
+TUNING = os.path.join(ROOT, "paper_1402_3010_amd", "tuning", "gfx950.json")
 WORKLOADS = {
     "c1": "n=2,000 m=10,000 nnz/vector uniform 10..60, Zipf s=1.0, t=0.5",
     "c2": "n=100,000 m=200,000 nnz/vector lognormal mean 80 (5..2000), Zipf s=1.1",
@@ -184,6 +185,8 @@ def screen_bench(args):
     for mode, sd in (("plain", 0), ("screened", args.screen_dims)):
         ix = apss.Index.build(dev, t, screen_dims=sd)
         torch.cuda.synchronize()
+        res_tune = ix.autotune(t, budget_ms=30000.0, cache=TUNING)
+        log("%s tuning: %s" % (mode, res_tune))
         i0, _, _ = ix.join(t)
         cap = len(i0) + 1024
         oi = torch.empty(cap, dtype=torch.int32, device="cuda")
@@ -199,7 +202,7 @@ def screen_bench(args):
             ms.append(1000.0 * (time.perf_counter() - t0))
         st = ix.stats()
         outs[mode] = (oi[:cnt].cpu().numpy(), oj[:cnt].cpu().numpy(), osim[:cnt].cpu().numpy())
-        res[mode] = {"ms": float(np.median(ms)), "matches": cnt, "stats": st}
+        res[mode] = {"ms": float(np.median(ms)), "matches": cnt, "stats": st, "tuning": res_tune}
         log("%s join: %.1f ms, %d pairs" % (mode, res[mode]["ms"], cnt))
         ix.close()
         del oi, oj, osim
@@ -213,6 +216,7 @@ def screen_bench(args):
         "workload": "c4: n=%d m=%d nnz/vector lognormal mean 150 (5..2000), Zipf s=0.9, t=%.1f; head = %d densest "
                     "dimensions as bf16" % (V.n, V.m, float(t), args.screen_dims),
         "plain_ms": res["plain"]["ms"], "screened_ms": res["screened"]["ms"],
+        "plain_tuning": res["plain"]["tuning"], "screened_tuning": res["screened"]["tuning"],
         "speedup": res["plain"]["ms"] / res["screened"]["ms"], "identical_output": bool(identical),
         "matches": res["screened"]["matches"],
         "plain_posting_visits": res["plain"]["stats"]["posting_visits"],
@@ -391,6 +395,9 @@ def main():
     build_s = time.perf_counter() - t0
     log("index built: %s (%.2f s)" % (ix.sizes(), build_s))
     del rp, col, val
+    # tile variant and range width from the shipped tuning table (tuned here if absent)
+    tune = ix.autotune(t, budget_ms=60000.0, cache=TUNING)
+    log("tuning: %s" % tune)
 
     # size the outputs with a first call
     i0, j0, s0 = ix.join(t)
@@ -446,6 +453,7 @@ def main():
         "verified": stats["verified"],
         "band_rescored": stats["band"],
         "index_build_s": build_s,
+        "tuning": tune,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic(args.config, t, args.n),
