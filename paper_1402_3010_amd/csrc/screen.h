@@ -22,12 +22,14 @@ hipError_t launch_screen_select(const RowStat* rs, int64_t n, float t, uint64_t*
                                 hipStream_t s);
 // sorted keys -> row ids (sid) and head norms (nh), padded to Sp with -1 / 0
 hipError_t launch_screen_unpack(const uint64_t* keys, int64_t S, int64_t Sp, int32_t* sid, float* nh, hipStream_t s);
-// head components (rank < head) of the selected rows -> bf16 block X[Sp][ld] (zeroed before)
+// head components (rank < head) of the selected rows -> bf16 block of Sp x ld
+// (zeroed before), stored as contiguous panels of 128 rows x 32 columns,
+// panel (row tile, K step) at offset (tile * ld / 32 + step) * 4096
 hipError_t launch_screen_pack(const int64_t* rp, const RComp* rc, const int32_t* sid, int64_t S, int32_t head,
                               int32_t ld, uint16_t* X, hipStream_t s);
 
 struct ScreenArgs {
-  const uint16_t* X;   // [Sp][ld] bf16 bits
+  const uint16_t* X;   // Sp x ld bf16 bits in 128 x 32 panels (see launch_screen_pack)
   int32_t ld;          // multiple of kScreenK
   const float* nh;     // [Sp] head norms (rounded up), 0 for padding
   const int32_t* sid;  // [Sp] row ids

@@ -30,6 +30,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 #define LAUNCH1D(kern, nthreads, ...)                                                       \
   do {                                                                                      \
@@ -74,33 +75,48 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
+// Packed head block, tile-major: row a, head rank k sits in the panel of
+// (row tile a / 128, K step k / 32), each panel 128 rows x 32 bf16 stored
+// contiguously (8 KB), so every operand load of the screen kernel reads a
+// contiguous stream.
+__device__ __forceinline__ int64_t panel_index(int64_t a, int32_t k, int32_t nks) {
+  return ((((a >> 7) * nks + (k >> 5)) << 12) | ((a & 127) << 5)) | (k & 31);
+}
+
 __global__ void k_screen_pack(const int64_t* __restrict__ rp, const RComp* __restrict__ rc,
                               const int32_t* __restrict__ sid, int64_t S, int32_t head, int32_t ld,
                               uint16_t* __restrict__ X) {
+  const int32_t nks = ld >> 5;
   for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < S; a += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = sid[a];
     const int64_t b = rp[r], e = rp[r + 1];
-    uint16_t* row = X + a * (int64_t)ld;
     // rank-space rows are in rank order: the head is a prefix
     for (int64_t k = b; k < e; ++k) {
       const RComp c = rc[k];
       if (c.r >= head) break;
-      row[c.r] = bf16_rne(c.w);
+      X[panel_index(a, c.r, nks)] = bf16_rne(c.w);
     }
   }
 }
 
 // One workgroup (4 waves) per 128 x 128 output tile (I, J) of the packed
 // rows; wave w owns the 64 x 64 quarter (w / 2, w % 2) as 2 x 2 MFMA blocks
-// of 32 x 32 (v_mfma_f32_32x32x16_bf16, float accumulation).  Operands move
-// through LDS in K steps of 64, double-buffered via registers.  Lane l of a
+// of 32 x 32 (v_mfma_f32_32x32x16_bf16, float accumulation).  Lane l of a
 // 32 x 32 x 16 MFMA holds operand row (l % 32), k = 8 (l / 32) .. + 7; result
 // element r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
-constexpr int kLda = kScreenK + 8;  // LDS row pitch in bf16 (16 bytes of padding)
+//
+// K advances in steps of 32 through two LDS buffers.  Each buffer row is 32
+// bf16 = four 16-byte chunks; chunk c of row r is stored at position
+// c ^ ((r >> 2) & 3), so the 16 rows read by 16 lanes of one 128-bit LDS
+// read hit 16 different bank groups.  Global loads run two steps ahead in
+// two register sets (the loop is unrolled by two so the sets stay static).
+constexpr int kStepK = 32;
 
-__global__ __launch_bounds__(256) void k_screen_mfma(ScreenArgs a, int64_t chunk) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][kScreenTile * kLda];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kScreenTile * kLda];
+__device__ __forceinline__ int swz(int row, int c) { return row * 4 + (c ^ ((row >> 2) & 3)); }
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_screen_mfma(ScreenArgs a, int64_t chunk) {
+  __shared__ u32x4 As[2][kScreenTile * 4];
+  __shared__ u32x4 Bs[2][kScreenTile * 4];
   // the workgroups of one XCD (round-robin over blockIdx) take one
   // contiguous chunk of the tile list, which is ordered by I
   const int64_t ti = (int64_t)(blockIdx.x & 7u) * chunk + (int64_t)(blockIdx.x >> 3);
@@ -111,26 +127,30 @@ __global__ __launch_bounds__(256) void k_screen_mfma(ScreenArgs a, int64_t chunk
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-  const int nkb = a.ld / kScreenK;
+  const int nks = a.ld / kStepK;
 
-  uint4 ra[4], rb[4];
-  auto gload = [&](int kb) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = tid + 256 * u;
-      const int row = c >> 3, col = (c & 7) * 8;
-      ra[u] = *reinterpret_cast<const uint4*>(a.X + (a0 + row) * a.ld + kb * kScreenK + col);
-      rb[u] = *reinterpret_cast<const uint4*>(a.X + (b0 + row) * a.ld + kb * kScreenK + col);
-    }
+  // this thread's two chunks of each operand per step: rows tid / 4 and
+  // tid / 4 + 64, chunk tid % 4, in the contiguous 8 KB panel of the step
+  const int lrow = tid >> 2, lc = tid & 3;
+  const uint16_t* pa0 = a.X + (((int64_t)I * nks) << 12) + lrow * 32 + lc * 8;
+  const uint16_t* pa1 = pa0 + 64 * 32;
+  const uint16_t* pb0 = a.X + (((int64_t)J * nks) << 12) + lrow * 32 + lc * 8;
+  const uint16_t* pb1 = pb0 + 64 * 32;
+  const int s0 = swz(lrow, lc), s1 = swz(lrow + 64, lc);
+
+  u32x4 r0[4], r1[4];
+  auto ldg = [&](int ks, u32x4 (&r)[4]) {
+    const int64_t o = (int64_t)ks << 12;
+    r[0] = *reinterpret_cast<const u32x4*>(pa0 + o);
+    r[1] = *reinterpret_cast<const u32x4*>(pa1 + o);
+    r[2] = *reinterpret_cast<const u32x4*>(pb0 + o);
+    r[3] = *reinterpret_cast<const u32x4*>(pb1 + o);
   };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = tid + 256 * u;
-      const int row = c >> 3, col = (c & 7) * 8;
-      *reinterpret_cast<uint4*>(&As[buf][row * kLda + col]) = ra[u];
-      *reinterpret_cast<uint4*>(&Bs[buf][row * kLda + col]) = rb[u];
-    }
+  auto sts = [&](int buf, const u32x4 (&r)[4]) {
+    As[buf][s0] = r[0];
+    As[buf][s1] = r[1];
+    Bs[buf][s0] = r[2];
+    Bs[buf][s1] = r[3];
   };
 
   floatx16 acc[2][2];
@@ -141,28 +161,47 @@ __global__ __launch_bounds__(256) void k_screen_mfma(ScreenArgs a, int64_t chunk
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  const int frow = lane & 31, fk = 8 * (lane >> 5);
-  for (int kb = 0; kb < nkb; ++kb) {
-    const int cur = kb & 1;
-    if (kb + 1 < nkb) gload(kb + 1);
+  const int frow = lane & 31, fh = lane >> 5;
+  auto compute = [&](int buf) {
 #pragma unroll
-    for (int kk = 0; kk < kScreenK / 16; ++kk) {
+    for (int kk = 0; kk < kStepK / 16; ++kk) {
       bf16x8 fa[2], fb[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        fa[i] = *reinterpret_cast<const bf16x8*>(&As[cur][(wr + 32 * i + frow) * kLda + 16 * kk + fk]);
+      for (int i = 0; i < 2; ++i) {
+        const u32x4 v = As[buf][swz(wr + 32 * i + frow, 2 * kk + fh)];
+        fa[i] = __builtin_bit_cast(bf16x8, v);
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        fb[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][(wc + 32 * j + frow) * kLda + 16 * kk + fk]);
+      for (int j = 0; j < 2; ++j) {
+        const u32x4 v = Bs[buf][swz(wc + 32 * j + frow, 2 * kk + fh)];
+        fb[j] = __builtin_bit_cast(bf16x8, v);
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
-    if (kb + 1 < nkb) lstore(cur ^ 1);
+  };
+
+  // prologue: step 0 in LDS, step 1 in flight (ld is a multiple of 64, so
+  // the number of steps is even and at least 2).  The loads are issued
+  // unconditionally (past the end they re-read the last panel) so that no
+  // branch merge forces an early wait on them.
+  ldg(0, r0);
+  ldg(1, r1);
+  sts(0, r0);
+  __syncthreads();
+  const int last = nks - 1;
+  for (int ks = 0; ks < nks; ks += 2) {
+    // even step ks: r1 holds step ks + 1, r0 is free
+    ldg(ks + 2 < last ? ks + 2 : last, r0);
+    compute(0);
+    sts(1, r1);
+    __syncthreads();
+    // odd step ks + 1: r0 holds step ks + 2, r1 is free
+    ldg(ks + 3 < last ? ks + 3 : last, r1);
+    compute(1);
+    sts(0, r0);
     __syncthreads();
   }
 
