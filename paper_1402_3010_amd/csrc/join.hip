@@ -115,6 +115,7 @@ struct Smem {
   int32_t lnext;   // next long segment to hand out
   int32_t qcount;
   int32_t ovf;
+  int32_t vtot;    // list entries of the tile in the item's range (staged tiles)
   int64_t item;
   unsigned long long cnt[C_NUM];
 };
@@ -179,6 +180,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     sm.lnext = 0;
     sm.qcount = 0;
     sm.ovf = 0;
+    sm.vtot = 0;
   }
   for (int e = tid; e < QT * RD; e += NT) sm.qd[e] = 0.0f;
   __syncthreads();
@@ -212,20 +214,23 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   uint32_t hn[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) hn[j] = 0;
+  int32_t vmine = 0;  // this thread's share of the item's list entries
   if (b_begin < b_end) {
     for (int64_t k = tid; k < tile_nnz; k += NT) {
       const RComp c = a.qrc[qbase + k];
       const int qi = find_slot(qbase + k);
       if (c.r < RD) sm.qd[qi * RD + c.r] = c.w;
-      uint32_t p0, ny = 0;
-      bool dead = false;  // no list entry in the item's corpus range
+      uint32_t p0, p1, ny = 0;
       if (c.r < a.H) {
         p0 = a.hoff[b_begin * (int64_t)a.H + c.r];
-        dead = a.hoff[b_end * (int64_t)a.H + c.r] == p0;
+        p1 = a.hoff[b_end * (int64_t)a.H + c.r];
       } else {
         p0 = a.toff[R * (int64_t)a.m_tail + (c.r - a.H)];
+        p1 = a.toff[(R + 1) * (int64_t)a.m_tail + (c.r - a.H)];
         ny = (int64_t)p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
       }
+      const bool dead = p1 == p0;  // no list entry in the item's corpus range
+      vmine += (int32_t)(p1 - p0);
       if (staged) {
         sm.qrow[k] = c;
         sm.cqi[k] = (uint8_t)qi;
@@ -241,6 +246,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       }
     }
   }
+  if (vmine) atomicAdd(&sm.vtot, vmine);
   __syncthreads();
 
   // q[r] for the query in slot qi (0 if absent)
@@ -257,8 +263,276 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   };
 
 
-  for (int64_t b = b_begin; b < b_end; ++b) {
+  // ------------------------------------------------------------ verify, rescore
+  // survivors in sm.sq name rows by their offset from dbase
+  int64_t dbase = 0;
+  auto drain = [&]() {
+    const int ns = uni(sm.qcount < SQ ? sm.qcount : SQ);
+    // verify s = A + dot(q, y'); y' is the first cut components of the row,
+    // densest dimension first.  Few survivors: one wave per survivor, lanes
+    // over y' (short latency chain); many: one lane per survivor.
+    if (ns <= 4 * NW) {
+      for (int e = wave; e < ns; e += NW) {
+        const uint4 it = sm.sq[e];
+        const int qi = (int)(it.x >> 16);
+        uint32_t cut = it.w & 0xFFFFu;
+        if ((it.w >> 16) == 0xFFFFu) cut = (uint32_t)a.rs[dbase + (it.x & 0xFFFFu)].cut;
+        float part = 0.0f;
+        for (uint32_t k = (uint32_t)lane; k < cut; k += 64) {
+          const RComp c = a.rc[it.z + k];
+          part += qlookup(qi, c.r) * c.w;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+        const float sc = (float)it.y * kInvFix + part;
+        if (lane == 0) {
+          if (sc >= sm.qt[qi] - kSlack) ++c_ver;
+          else sm.sq[e].y = 0u;
+        }
+      }
+    } else
+    for (int e = tid; e < ns; e += NT) {
+      const uint4 it = sm.sq[e];
+      const int qi = (int)(it.x >> 16);
+      uint32_t cut = it.w & 0xFFFFu;
+      if ((it.w >> 16) == 0xFFFFu) cut = (uint32_t)a.rs[dbase + (it.x & 0xFFFFu)].cut;
+      float sc = (float)it.y * kInvFix;
+      for (uint32_t k0 = 0; k0 < cut; k0 += 4) {
+        RComp c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = a.rc[it.z + (k0 + u < cut ? k0 + u : cut - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k0 + u < cut) sc += qlookup(qi, c[u].r) * c[u].w;
+      }
+      if (sc >= sm.qt[qi] - kSlack) ++c_ver;
+      else sm.sq[e].y = 0u;
+    }
+    __syncthreads();
+    // rescore: one wave per verified pair
+    for (int base = wave * 64; base < ns; base += NT) {
+      const int e = base + lane;
+      uint64_t fm = __ballot(e < ns && sm.sq[e < ns ? e : 0].y != 0u);
+      while (fm) {
+        const int l = __ffsll((unsigned long long)fm) - 1;
+        fm &= fm - 1;
+        const uint4 it = sm.sq[base + l];
+        const int qi = (int)(it.x >> 16);
+        const int64_t y = dbase + (int64_t)(it.x & 0xFFFFu);
+        const int64_t ys = it.z;
+        int ylen = (int)(it.w >> 16);
+        if (ylen == 0xFFFF) ylen = (int)(a.rp[y + 1] - a.rp[y]);
+        const RComp* yrow = a.rc + ys;
+        auto look = [&](int32_t r) { return qlookup(qi, r); };
+        const float s32 = wave_dot2(yrow, ylen, lane, look);
+        float sim;
+        bool banded;
+        const bool keep = wave_decide(yrow, ylen, lane, look, s32, sm.qt[qi], &sim, &banded);
+        if (banded && lane == 0) ++c_band;
+        if (keep && lane == 0) {
+          const uint64_t qid = (uint64_t)(q0 + qi);
+          const uint64_t key = a.triangle ? (((uint64_t)y << a.bj) | qid) : ((qid << a.bj) | (uint64_t)y);
+          const unsigned long long idx = atomicAdd(&a.counters[C_MATCHES], 1ull);
+          if ((int64_t)idx < a.cap) {
+            a.out_key[idx] = key;
+            a.out_sim[idx] = sim;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      sm.qcount = 0;
+      sm.ovf = 0;
+    }
+    __syncthreads();
+  };
+
+
+  // ------------------------------------------------------------ sparse items
+  // An item whose lists hold at most HS / 2 entries in the whole range is
+  // accumulated at once into an open-addressing hash table in LDS (keys and
+  // fixed-point scores in the two halves of the accumulator array, key 0 =
+  // free), and only the touched slots are filtered.  The table never fills,
+  // so every probe sequence ends.  Other items sweep the range block by block.
+  constexpr int HS = QT * CB / 2;
+  constexpr int HBITS = (HS == 8192) ? 13 : (HS == 4096) ? 12 : (HS == 2048) ? 11 : 10;
+  static_assert((1 << HBITS) == HS, "hash table size");
+  const bool hashed = staged && b_begin < b_end && (int64_t)a.K * CB <= 65536 && uni(sm.vtot) <= HS / 2;
+  if (hashed) {
+    uint32_t* const hval = sm.acc;
+    uint32_t* const hkey = sm.acc + HS;
+    const int64_t rbeg = b_begin * CB;
+    // one segment per live component: its list entries in the range
+    for (int64_t k = tid; k < tile_nnz; k += NT) {
+      const uint2 cu = sm.cur[k];
+      if (cu.x == kDead) continue;
+      const RComp c = sm.qrow[k];
+      const uint32_t p1 = c.r < a.H ? a.hoff[b_end * (int64_t)a.H + c.r]
+                                    : a.toff[(R + 1) * (int64_t)a.m_tail + (c.r - a.H)];
+      if (p1 > cu.x) {
+        const int slot = atomicAdd(&sm.nshort, 1);
+        Seg sg;
+        sg.pos = cu.x;
+        sg.lenq = (p1 - cu.x) | ((uint32_t)sm.cqi[k] << 16);
+        sg.q = q15(c.w);
+        sm.seg[QB - 1 - slot] = sg;
+      }
+    }
+    __syncthreads();
+    const int ns = uni(sm.nshort);
+    Seg* const sseg = sm.seg + (QB - ns);
+    {
+      int loc[KMAX];
+      int run = 0;
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        const int e = tid * KMAX + j;
+        loc[j] = run;
+        run += e < ns ? (int)(sseg[e].lenq & 0xFFFFu) : 0;
+      }
+      int incl = run;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+      }
+      if (lane == 63) sm.wsum[wave] = incl;
+      __syncthreads();
+      int woff = 0;
+      for (int w = 0; w < wave; ++w) woff += sm.wsum[w];
+      const int excl = woff + incl - run;
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        const int e = tid * KMAX + j;
+        if (e < ns) sm.segpre[e] = excl + loc[j];
+      }
+      if (tid == NT - 1) sm.segpre[ns] = woff + incl;
+    }
+    __syncthreads();
+    const int L = uni(sm.segpre[ns]);
+    if (tid == 0) {
+      c_visit += (unsigned long long)L;
+      sm.nshort = 0;
+    }
+    // every entry of every segment, split evenly over the waves
+    {
+      const int per = (((L + NW - 1) / NW) + 63) & ~63;
+      const int vbeg = wave * per;
+      const int vend = (vbeg + per) < L ? (vbeg + per) : L;
+      if (vbeg < vend) {
+        int lo = 0, hi = ns - 1;  // last segment starting at or before vbeg
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (sm.segpre[mid] <= vbeg) lo = mid;
+          else hi = mid - 1;
+        }
+        int s = lo, cs = -1, pre = 0;
+        Seg S = {0u, 0u, 0u};
+        for (int base = vbeg; base < vend; base += 64 * U) {
+          uint32_t pos[U], qwb[U];
+          int qs[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int vr = base + u * 64 + lane;
+            const int v = vr < vend ? vr : vend - 1;
+            while (sm.segpre[s + 1] <= v) ++s;
+            if (s != cs) {
+              S = sseg[s];
+              pre = sm.segpre[s];
+              cs = s;
+            }
+            pos[u] = S.pos + (uint32_t)(v - pre);
+            qwb[u] = S.q;
+            qs[u] = vr < vend ? (int)(S.lenq >> 16) : -1;
+          }
+          uint32_t p[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) p[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, (int)(pos[u] * 4u), 0, 0);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (qs[u] >= 0) {
+              const uint32_t key = (((uint32_t)qs[u] << 16) | ((p[u] - (uint32_t)rbeg) & 0xFFFFu)) + 1u;
+              uint32_t h = (key * 0x9E3779B1u) >> (32 - HBITS);
+              for (;;) {
+                const uint32_t old = atomicCAS(&hkey[h], 0u, key);
+                if (old == 0u || old == key) {
+                  atomicAdd(&hval[h], packed_product(qwb[u], p[u]));
+                  break;
+                }
+                h = (h + 1u) & (uint32_t)(HS - 1);
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // filter the touched slots; survivors that do not fit the queue stay
+    // in the table for the next pass
+    dbase = rbeg;
+    for (;;) {
+#pragma unroll 1
+      for (int h0 = 0; h0 < HS; h0 += NT) {
+        const int h = h0 + tid;
+        const uint32_t kk = hkey[h];
+        bool want = false, retry = false;
+        int qi = 0, yl = 0;
+        uint32_t av = 0u, yst = 0u, packed = 0u;
+        if (kk) {
+          qi = (int)((kk - 1u) >> 16);
+          yl = (int)((kk - 1u) & 0xFFFFu);
+          const int64_t y = rbeg + yl;
+          av = hval[h];
+          if (y < a.n && !(a.triangle && y >= q0 + qi)) {
+            const RowStat st = a.rs[y];
+            const uint32_t r0 = (uint32_t)a.rp[y];
+            const int ylen = (int)((uint32_t)a.rp[y + 1] - r0);
+            yst = r0;
+            packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
+            const float A = (float)av * kInvFix;
+            const float thr = sm.qt[qi] - kSlack;
+            const float qm = sm.qmw[qi];
+            const int ql = sm.qlen[qi];
+            const float mn = (float)(st.cut < ql ? st.cut : ql);
+            want = ((float)ylen * qm >= thr) && (A + mn * qm * st.pmw >= thr) && (A + sm.qpn[qi] * st.pnrm >= thr);
+            ++c_cand;
+          }
+        }
+        const uint64_t wm = __ballot(want);
+        if (wm) {
+          int qb = 0;
+          if (lane == 0) qb = atomicAdd(&sm.qcount, (int)__popcll(wm));
+          qb = __shfl(qb, 0);
+          if (want) {
+            const int slot = qb + (int)__popcll(wm & lt);
+            if (slot < SQ) {
+              sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av, yst, packed);
+              ++c_surv;
+            } else {
+              retry = true;
+              --c_cand;
+              sm.ovf = 1;
+            }
+          }
+        }
+        if (kk && !retry) {
+          hkey[h] = 0u;
+          hval[h] = 0u;
+        }
+      }
+      __syncthreads();
+      const int o = uni(sm.ovf);
+      const int qc = uni(sm.qcount);
+      __syncthreads();
+      if (qc > 0) drain();
+      if (!o) break;
+    }
+  }
+
+  for (int64_t b = (hashed ? b_end : b_begin); b < b_end; ++b) {
     const int64_t blk0 = b * CB;
+    dbase = blk0;
     const int64_t blk1 = (blk0 + CB) < a.n ? (blk0 + CB) : a.n;
     const uint32_t* hend = a.hoff + (b + 1) * (int64_t)a.H;   // end of each dense list's block segment
     const uint32_t* hnext = a.hoff + (b + 2) * (int64_t)a.H;  // same for the next block (b < last_b)
@@ -537,89 +811,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       }
       __syncthreads();
     }
-
-    // ------------------------------------------------------------ filter, verify, rescore
-    auto drain = [&]() {
-      const int ns = uni(sm.qcount < SQ ? sm.qcount : SQ);
-      // verify s = A + dot(q, y'); y' is the first cut components of the row,
-      // densest dimension first.  Few survivors: one wave per survivor, lanes
-      // over y' (short latency chain); many: one lane per survivor.
-      if (ns <= 4 * NW) {
-        for (int e = wave; e < ns; e += NW) {
-          const uint4 it = sm.sq[e];
-          const int qi = (int)(it.x >> 16);
-          uint32_t cut = it.w & 0xFFFFu;
-          if ((it.w >> 16) == 0xFFFFu) cut = (uint32_t)a.rs[blk0 + (it.x & 0xFFFFu)].cut;
-          float part = 0.0f;
-          for (uint32_t k = (uint32_t)lane; k < cut; k += 64) {
-            const RComp c = a.rc[it.z + k];
-            part += qlookup(qi, c.r) * c.w;
-          }
-#pragma unroll
-          for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
-          const float sc = (float)it.y * kInvFix + part;
-          if (lane == 0) {
-            if (sc >= sm.qt[qi] - kSlack) ++c_ver;
-            else sm.sq[e].y = 0u;
-          }
-        }
-      } else
-      for (int e = tid; e < ns; e += NT) {
-        const uint4 it = sm.sq[e];
-        const int qi = (int)(it.x >> 16);
-        uint32_t cut = it.w & 0xFFFFu;
-        if ((it.w >> 16) == 0xFFFFu) cut = (uint32_t)a.rs[blk0 + (it.x & 0xFFFFu)].cut;
-        float sc = (float)it.y * kInvFix;
-        for (uint32_t k0 = 0; k0 < cut; k0 += 4) {
-          RComp c[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) c[u] = a.rc[it.z + (k0 + u < cut ? k0 + u : cut - 1)];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (k0 + u < cut) sc += qlookup(qi, c[u].r) * c[u].w;
-        }
-        if (sc >= sm.qt[qi] - kSlack) ++c_ver;
-        else sm.sq[e].y = 0u;
-      }
-      __syncthreads();
-      // rescore: one wave per verified pair
-      for (int base = wave * 64; base < ns; base += NT) {
-        const int e = base + lane;
-        uint64_t fm = __ballot(e < ns && sm.sq[e < ns ? e : 0].y != 0u);
-        while (fm) {
-          const int l = __ffsll((unsigned long long)fm) - 1;
-          fm &= fm - 1;
-          const uint4 it = sm.sq[base + l];
-          const int qi = (int)(it.x >> 16);
-          const int64_t y = blk0 + (int64_t)(it.x & 0xFFFFu);
-          const int64_t ys = it.z;
-          int ylen = (int)(it.w >> 16);
-          if (ylen == 0xFFFF) ylen = (int)(a.rp[y + 1] - a.rp[y]);
-          const RComp* yrow = a.rc + ys;
-          auto look = [&](int32_t r) { return qlookup(qi, r); };
-          const float s32 = wave_dot2(yrow, ylen, lane, look);
-          float sim;
-          bool banded;
-          const bool keep = wave_decide(yrow, ylen, lane, look, s32, sm.qt[qi], &sim, &banded);
-          if (banded && lane == 0) ++c_band;
-          if (keep && lane == 0) {
-            const uint64_t qid = (uint64_t)(q0 + qi);
-            const uint64_t key = a.triangle ? (((uint64_t)y << a.bj) | qid) : ((qid << a.bj) | (uint64_t)y);
-            const unsigned long long idx = atomicAdd(&a.counters[C_MATCHES], 1ull);
-            if ((int64_t)idx < a.cap) {
-              a.out_key[idx] = key;
-              a.out_sim[idx] = sim;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      if (tid == 0) {
-        sm.qcount = 0;
-        sm.ovf = 0;
-      }
-      __syncthreads();
-    };
 
     for (bool first = true;; first = false) {
       if (!first) load_rows(0);

@@ -134,7 +134,7 @@ extern "C" int apss_autotune(apss_index* ix, float t, double budget_ms, const ch
   best.ms = INFINITY;
   const auto start = std::chrono::steady_clock::now();
   // the current configuration first, so that a small budget still gives a valid choice
-  const long long ranges[] = {8192, 16384, 4096};
+  const long long ranges[] = {8192, 16384, 4096, 2048};
   int tried = 0;
   for (int pass = 0; pass < 2; ++pass) {
     for (int v = 0; v < join_num_variants(); ++v) {

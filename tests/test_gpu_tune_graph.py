@@ -38,7 +38,7 @@ def test_autotune_choice_and_cache(apss, tmp_path, name, n, t, sd):
         before = ix.join(t)
         r = ix.autotune(t, cache=cache)
         assert r["from_cache"] == 0 and r["tried"] >= 4 and r["cache_write_failed"] == 0
-        assert 0 <= r["variant"] < 4 and r["range_rows"] in (4096, 8192, 16384) and r["ms"] > 0
+        assert 0 <= r["variant"] < 4 and r["range_rows"] in (2048, 4096, 8192, 16384) and r["ms"] > 0
         after = ix.join(t)
         assert same(before, after)
     finally:
