@@ -116,6 +116,7 @@ struct Smem {
   int32_t qcount;
   int32_t ovf;
   int32_t vtot;    // list entries of the tile in the item's range (staged tiles)
+  int32_t slot;    // range slot of the current item in its queue
   int64_t item;
   unsigned long long cnt[C_NUM];
 };
@@ -150,18 +151,30 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     const int x = (xcd + qx) & 7;
     const int64_t* cum = a.qcum + (int64_t)x * (a.nrx + 1);
     const int64_t total = cum[a.nrx];
+    __syncthreads();
+    if (tid == 0) sm.item = (int64_t)atomicAdd(&a.qctr[x], 1u);
     for (;;) {
-      __syncthreads();
-      if (tid == 0) sm.item = (int64_t)atomicAdd(&a.qctr[x], 1u);
       __syncthreads();
       const int64_t it = uni64(sm.item);
       if (it >= total) break;
-      int lo_j = 0, hi_j = (int)a.nrx - 1;  // range slot j with cum[j] <= it < cum[j + 1]
-      while (lo_j < hi_j) {
-        const int mid = (lo_j + hi_j + 1) >> 1;
-        if (cum[mid] <= it) lo_j = mid;
-        else hi_j = mid - 1;
+      // the next item's index is fetched now and published at the end of
+      // this item, so the atomic's latency overlaps the work
+      uint32_t next_item = 0;
+      if (tid == 0) next_item = atomicAdd(&a.qctr[x], 1u);
+      // range slot j with cum[j] <= it < cum[j + 1]: wave 0 compares 64
+      // slots per load round (cum is non-decreasing, cum[0] = 0)
+      if (wave == 0) {
+        int j = 0;
+        for (int c0 = 0; c0 < (int)a.nrx; c0 += 64) {
+          const int jj = c0 + lane;
+          const uint64_t m = __ballot(jj < (int)a.nrx && cum[jj] <= it);
+          if (m) j = c0 + 63 - (int)__builtin_clzll(m);
+          if (m != ~0ull) break;
+        }
+        if (lane == 0) sm.slot = j;
       }
+      __syncthreads();
+      const int lo_j = uni(sm.slot);
       const int64_t R = (int64_t)x + 8 * (int64_t)lo_j;
       const int64_t tile = a.ntiles - 1 - (it - cum[lo_j]);
       const int64_t b_begin = R * a.K;
@@ -187,16 +200,21 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   const int64_t qbase = uni64(sm.qoff[0]);
   const int64_t tile_nnz = uni64(sm.qoff[qn]) - qbase;
   const bool staged = tile_nnz <= QB;
+  // first component of each query with rank >= RD (searched in global
+  // memory only for tiles too large to stage)
+  auto find_head = [&](const RComp* row, int len) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (row[mid].r < RD) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
   if (tid < qn) {
     const int64_t r0 = sm.qoff[tid], r1 = sm.qoff[tid + 1];
     sm.qlen[tid] = (int32_t)(r1 - r0);
-    int64_t lo = r0, hi = r1;  // first component with rank >= RD
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (a.qrc[mid].r < RD) lo = mid + 1;
-      else hi = mid;
-    }
-    sm.qhead[tid] = (int32_t)(lo - r0);
+    if (!staged) sm.qhead[tid] = find_head(a.qrc + r0, (int)(r1 - r0));
   }
   auto find_slot = [&](int64_t k) {
     int qi = 0;
@@ -227,13 +245,24 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       } else {
         p0 = a.toff[R * (int64_t)a.m_tail + (c.r - a.H)];
         p1 = a.toff[(R + 1) * (int64_t)a.m_tail + (c.r - a.H)];
-        ny = (int64_t)p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
+        // the first entry's vector id is needed only on the block path; for
+        // staged tiles it is loaded once the item is known to take that path
+        if (!staged) ny = (int64_t)p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
       }
       const bool dead = p1 == p0;  // no list entry in the item's corpus range
       vmine += (int32_t)(p1 - p0);
       if (staged) {
         sm.qrow[k] = c;
         sm.cqi[k] = (uint8_t)qi;
+        // the component's entries in the whole range, for a hashed item
+        // (whose segments are all short enough for the 16-bit length)
+        if (!dead) {
+          Seg sg;
+          sg.pos = p0;
+          sg.lenq = ((p1 - p0) & 0xFFFFu) | ((uint32_t)qi << 16);
+          sg.q = q15(c.w);
+          sm.seg[QB - 1 - atomicAdd(&sm.nshort, 1)] = sg;
+        }
         sm.cur[k] = make_uint2(dead ? kDead : p0, ny);
         if (c.r < a.H && !dead) {
 #pragma unroll
@@ -247,6 +276,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     }
   }
   if (vmine) atomicAdd(&sm.vtot, vmine);
+  __syncthreads();
+  if (staged && tid < qn) sm.qhead[tid] = find_head(sm.qrow + (sm.qoff[tid] - qbase), sm.qlen[tid]);
   __syncthreads();
 
   // q[r] for the query in slot qi (0 if absent)
@@ -350,7 +381,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 
 
   // ------------------------------------------------------------ sparse items
-  // An item whose lists hold at most HS / 2 entries in the whole range is
+  // An item whose lists hold at most 3 HS / 4 entries in the whole range is
   // accumulated at once into an open-addressing hash table in LDS (keys and
   // fixed-point scores in the two halves of the accumulator array, key 0 =
   // free), and only the touched slots are filtered.  The table never fills,
@@ -358,28 +389,12 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   constexpr int HS = QT * CB / 2;
   constexpr int HBITS = (HS == 8192) ? 13 : (HS == 4096) ? 12 : (HS == 2048) ? 11 : 10;
   static_assert((1 << HBITS) == HS, "hash table size");
-  const bool hashed = staged && b_begin < b_end && (int64_t)a.K * CB <= 65536 && uni(sm.vtot) <= HS / 2;
+  const bool hashed = staged && b_begin < b_end && (int64_t)a.K * CB <= 65536 && uni(sm.vtot) <= HS - HS / 4;
   if (hashed) {
     uint32_t* const hval = sm.acc;
     uint32_t* const hkey = sm.acc + HS;
     const int64_t rbeg = b_begin * CB;
-    // one segment per live component: its list entries in the range
-    for (int64_t k = tid; k < tile_nnz; k += NT) {
-      const uint2 cu = sm.cur[k];
-      if (cu.x == kDead) continue;
-      const RComp c = sm.qrow[k];
-      const uint32_t p1 = c.r < a.H ? a.hoff[b_end * (int64_t)a.H + c.r]
-                                    : a.toff[(R + 1) * (int64_t)a.m_tail + (c.r - a.H)];
-      if (p1 > cu.x) {
-        const int slot = atomicAdd(&sm.nshort, 1);
-        Seg sg;
-        sg.pos = cu.x;
-        sg.lenq = (p1 - cu.x) | ((uint32_t)sm.cqi[k] << 16);
-        sg.q = q15(c.w);
-        sm.seg[QB - 1 - slot] = sg;
-      }
-    }
-    __syncthreads();
+    // the live segments written at staging, contiguous at the back of seg[]
     const int ns = uni(sm.nshort);
     Seg* const sseg = sm.seg + (QB - ns);
     {
@@ -411,10 +426,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     }
     __syncthreads();
     const int L = uni(sm.segpre[ns]);
-    if (tid == 0) {
-      c_visit += (unsigned long long)L;
-      sm.nshort = 0;
-    }
+    if (tid == 0) c_visit += (unsigned long long)L;
     // every entry of every segment, split evenly over the waves
     {
       const int per = (((L + NW - 1) / NW) + 63) & ~63;
@@ -530,6 +542,18 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     }
   }
 
+  if (!hashed && b_begin < b_end) {
+    // the block path builds its own segments, and walks the sparse lists
+    // from the vector id of their first entry in the range
+    if (tid == 0) sm.nshort = 0;
+    if (staged) {
+      for (int64_t k = tid; k < tile_nnz; k += NT) {
+        const uint2 cu = sm.cur[k];
+        if (cu.x != kDead && sm.qrow[k].r >= a.H) sm.cur[k] = make_uint2(cu.x, a.post[cu.x].y);
+      }
+    }
+    __syncthreads();
+  }
   for (int64_t b = (hashed ? b_end : b_begin); b < b_end; ++b) {
     const int64_t blk0 = b * CB;
     dbase = blk0;
@@ -870,6 +894,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     }
   }
 
+      if (tid == 0) sm.item = (int64_t)next_item;
     }  // items of queue x
   }    // queues
 
