@@ -294,6 +294,60 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   };
 
 
+  // Every entry of the short segments sseg[0..ns) (exclusive prefix sums of
+  // their lengths in sm.segpre, L entries in all): wave w takes a contiguous
+  // slice, 64 consecutive entries per load (lane l, entry c + l), U loads in
+  // flight per lane.  The segment of each entry: lane j holds the start of
+  // the j-th segment after the one holding the chunk's first entry (starts
+  // increase with j), and every lane counts the starts at or before its own
+  // entry by a binary search over the lanes (six shuffles).  Segments are
+  // never empty, so at most 63 of them start inside a chunk.
+  // add(qi, packed entry, query weight).
+  auto stream_short = [&](const Seg* sseg, int ns, int L, auto&& add) {
+    const int per = (((L + NW - 1) / NW) + 63) & ~63;
+    const int vbeg = wave * per;
+    const int vend = (vbeg + per) < L ? (vbeg + per) : L;
+    if (vbeg >= vend) return;
+    int lo = 0, hi = ns - 1;  // segment holding entry vbeg
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sm.segpre[mid] <= vbeg) lo = mid;
+      else hi = mid - 1;
+    }
+    int sa = lo;  // segment holding the current chunk's first entry
+    for (int base = vbeg; base < vend; base += 64 * U) {
+      uint32_t pos[U], qwb[U];
+      int qs[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = base + u * 64;
+        const int sj = sa + 1 + lane;
+        const int rel = sj < ns ? sm.segpre[sj] - c : 0x7FFFFFFF;  // >= 1: segment sa holds entry c
+        int k = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+          const int r = __shfl(rel, k + step - 1, 64);
+          if (r <= lane) k += step;
+        }
+        const int sg = sa + k;
+        const Seg S = sseg[sg];
+        const int v = c + lane;
+        pos[u] = S.pos + (uint32_t)(v - sm.segpre[sg]);
+        qwb[u] = S.q;
+        qs[u] = v < vend ? (int)(S.lenq >> 16) : -1;
+        // the next chunk starts in the last entry's segment or the one after
+        const int last = __shfl(sg, 63, 64);
+        sa = (last + 1 < ns && sm.segpre[last + 1] <= c + 64) ? last + 1 : last;
+      }
+      uint32_t pv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pv[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, (int)(pos[u] * 4u), 0, 0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (qs[u] >= 0) add(qs[u], pv[u], qwb[u]);
+    }
+  };
+
   // ------------------------------------------------------------ verify, rescore
   // survivors in sm.sq name rows by their offset from dbase
   int64_t dbase = 0;
@@ -428,57 +482,18 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     const int L = uni(sm.segpre[ns]);
     if (tid == 0) c_visit += (unsigned long long)L;
     // every entry of every segment, split evenly over the waves
-    {
-      const int per = (((L + NW - 1) / NW) + 63) & ~63;
-      const int vbeg = wave * per;
-      const int vend = (vbeg + per) < L ? (vbeg + per) : L;
-      if (vbeg < vend) {
-        int lo = 0, hi = ns - 1;  // last segment starting at or before vbeg
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (sm.segpre[mid] <= vbeg) lo = mid;
-          else hi = mid - 1;
+    stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw) {
+      const uint32_t key = (((uint32_t)qi << 16) | ((p - (uint32_t)rbeg) & 0xFFFFu)) + 1u;
+      uint32_t h = (key * 0x9E3779B1u) >> (32 - HBITS);
+      for (;;) {
+        const uint32_t old = atomicCAS(&hkey[h], 0u, key);
+        if (old == 0u || old == key) {
+          atomicAdd(&hval[h], packed_product(qw, p));
+          break;
         }
-        int s = lo, cs = -1, pre = 0;
-        Seg S = {0u, 0u, 0u};
-        for (int base = vbeg; base < vend; base += 64 * U) {
-          uint32_t pos[U], qwb[U];
-          int qs[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int vr = base + u * 64 + lane;
-            const int v = vr < vend ? vr : vend - 1;
-            while (sm.segpre[s + 1] <= v) ++s;
-            if (s != cs) {
-              S = sseg[s];
-              pre = sm.segpre[s];
-              cs = s;
-            }
-            pos[u] = S.pos + (uint32_t)(v - pre);
-            qwb[u] = S.q;
-            qs[u] = vr < vend ? (int)(S.lenq >> 16) : -1;
-          }
-          uint32_t p[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) p[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, (int)(pos[u] * 4u), 0, 0);
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            if (qs[u] >= 0) {
-              const uint32_t key = (((uint32_t)qs[u] << 16) | ((p[u] - (uint32_t)rbeg) & 0xFFFFu)) + 1u;
-              uint32_t h = (key * 0x9E3779B1u) >> (32 - HBITS);
-              for (;;) {
-                const uint32_t old = atomicCAS(&hkey[h], 0u, key);
-                if (old == 0u || old == key) {
-                  atomicAdd(&hval[h], packed_product(qwb[u], p[u]));
-                  break;
-                }
-                h = (h + 1u) & (uint32_t)(HS - 1);
-              }
-            }
-          }
-        }
+        h = (h + 1u) & (uint32_t)(HS - 1);
       }
-    }
+    });
     __syncthreads();
     // filter the touched slots; survivors that do not fit the queue stay
     // in the table for the next pass
@@ -722,47 +737,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       }
       // short segments: each wave takes a contiguous range of their visits;
       // every lane keeps U list loads in flight
-      {
-        const int per = (((L + NW - 1) / NW) + 63) & ~63;
-        const int vbeg = wave * per;
-        const int vend = (vbeg + per) < L ? (vbeg + per) : L;
-        if (vbeg < vend) {
-          int lo = 0, hi = ns - 1;  // last segment starting at or before vbeg
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sm.segpre[mid] <= vbeg) lo = mid;
-            else hi = mid - 1;
-          }
-          int s = lo, cs = -1, pre = 0;
-          Seg S = {0u, 0u, 0u};
-          for (int base = vbeg; base < vend; base += 64 * U) {
-            // resolve every visit's segment first (LDS only), then issue all
-            // list loads back to back with clamped addresses, then accumulate
-            uint32_t pos[U], qwb[U];
-            int qs[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const int vr = base + u * 64 + lane;
-              const int v = vr < vend ? vr : vend - 1;
-              while (sm.segpre[s + 1] <= v) ++s;
-              if (s != cs) {
-                S = sseg[s];
-                pre = sm.segpre[s];
-                cs = s;
-              }
-              pos[u] = S.pos + (uint32_t)(v - pre);
-              qwb[u] = S.q;
-              qs[u] = vr < vend ? (int)(S.lenq >> 16) : -1;
-            }
-            uint32_t p[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) p[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, (int)(pos[u] * 4u), 0, 0);
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-              if (qs[u] >= 0) atomicAdd(&sm.acc[qs[u] * CB + (int)(p[u] & (CB - 1))], packed_product(qwb[u], p[u]));
-          }
-        }
-      }
+      stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw) {
+        atomicAdd(&sm.acc[qi * CB + (int)(p & (CB - 1))], packed_product(qw, p));
+      });
       // long segments: wave w walks segments w, w + NW, ... in chunks of 64
       // entries (one entry per lane) with all bookkeeping uniform.  Two
       // batches of UL chunks alternate: the next batch's loads are issued
