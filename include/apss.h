@@ -61,8 +61,8 @@ typedef struct {
                             own L2 norm reaches t, so dot(q, x') < t for any unit query q and the
                             index answers apss_query; 0: the paper's cutoff only (join only) */
   int32_t variant;       /* compiled tile variant of the join kernel (queries per tile x corpus
-                            rows per block); -1 = the library's default.  The environment
-                            variable APSS_VARIANT overrides it. */
+                            rows per block): 0, 1 or 2 (3 is withdrawn: APSS_EINVAL); -1 = the
+                            library's default.  The environment variable APSS_VARIANT overrides it. */
   int32_t head_dims;     /* densest dimensions that get per-block list offsets (0 = default) */
   int32_t range_rows;    /* corpus rows per work item of the join (rounded down to a multiple of the
                             variant's block rows; 0 = default 8192).  The environment variable

@@ -588,6 +588,10 @@ int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, in
   apss_index* sx = ix->screen;
   hipStream_t s = ws.stream;
   *count = 0;
+  if (!screen_variant_ok(sx->variant)) {
+    set_error("tile variant %d is not available for the screened join", sx->variant);
+    return APSS_EINVAL;
+  }
   int rc = start_call(ws);
   if (rc) return rc;
   const int64_t n = sx->n;
@@ -1003,8 +1007,8 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
     }
     o = *opts;
   }
-  if (o.variant < -1 || o.variant >= join_num_variants()) {
-    set_error("variant %d outside [-1, %d)", o.variant, join_num_variants());
+  if (o.variant < -1 || o.variant >= join_num_variants() || (o.variant >= 0 && !variant_available(o.variant))) {
+    set_error("variant %d is not available (outside [-1, %d) or withdrawn)", o.variant, join_num_variants());
     return APSS_EINVAL;
   }
   if (o.range_rows < 0) {
@@ -1028,7 +1032,7 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
   ix->variant = o.variant >= 0 ? o.variant : 1;
   if (const char* ev = getenv("APSS_VARIANT")) {
     const int v = atoi(ev);
-    if (v >= 0 && v < join_num_variants()) ix->variant = v;
+    if (v >= 0 && v < join_num_variants() && variant_available(v)) ix->variant = v;
   }
   ix->range_rows = o.range_rows > 0 ? o.range_rows : default_range_rows(ix->variant);
   if (const char* ev = getenv("APSS_RANGE_ROWS")) {
@@ -1036,6 +1040,11 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
     if (rr > 0) ix->range_rows = rr;
   }
   (void)hipGetDevice(&ix->device);
+  if (o.screen_dims > 0 && !screen_variant_ok(ix->variant)) {
+    set_error("tile variant %d is not available for the screened join", ix->variant);
+    delete ix;
+    return APSS_EINVAL;
+  }
   int rc = build_impl(ix, row_ptr, col, val, on_device);
   if (!rc && o.screen_dims > 0) rc = build_screen(ix, (int32_t)std::min<int64_t>(o.screen_dims, m));
   if (rc) {

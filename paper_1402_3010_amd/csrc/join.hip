@@ -980,6 +980,8 @@ hipError_t launch_variant(const JoinArgs& a, int grid, hipStream_t s) {
 }
 
 hipError_t launch_join(const JoinArgs& a, int variant, int grid, hipStream_t s) {
+  // variant 3 is withdrawn (see variant_available in the host library)
+  if (variant == 3) return hipErrorInvalidValue;
   if (a.ntiles <= 0 || grid <= 0) return hipSuccess;
   switch (variant) {
     case 0: return launch_variant<V0>(a, grid, s);

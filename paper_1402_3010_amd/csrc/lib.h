@@ -179,6 +179,12 @@ int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_ro
 // *count.  cap_hint: pair capacity to start with (grown and rerun on overflow).
 int run_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, float t, const float* qt_dev,
              int64_t cap_hint, int64_t* count);
+// Tile variants that may be launched.  Variant 3 (4 queries x 2048 rows,
+// 256 threads) faulted on the GPU (memory aperture violation) in two tuning
+// runs on the 500k-vector workloads, intermittently and without an
+// identified cause, so it is refused everywhere until that is found.
+inline bool variant_available(int variant) { return variant != 3; }
+inline bool screen_variant_ok(int variant) { return variant_available(variant); }
 // Screened self-join of an index built with screen_dims > 0 (ix->screen set).
 int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, int64_t* count);
 // Unpack the sorted raw pairs into device arrays / library-owned host arrays.

@@ -116,7 +116,7 @@ extern "C" int apss_autotune(apss_index* ix, float t, double budget_ms, const ch
     cache = read_cache(cache_path);
     auto it = cache.find(key);
     if (it != cache.end() && it->second.variant >= 0 && it->second.variant < join_num_variants() &&
-        it->second.range_rows > 0) {
+        variant_available(it->second.variant) && it->second.range_rows > 0) {
       target->variant = it->second.variant;
       target->range_rows = it->second.range_rows;
       out->variant = it->second.variant;
@@ -144,6 +144,7 @@ extern "C" int apss_autotune(apss_index* ix, float t, double budget_ms, const ch
         int qt = 0, cb = 0;
         (void)join_variant_geometry(v, &qt, &cb);
         if (rr < cb) continue;
+        if (!variant_available(v)) continue;
         const double spent =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - start).count();
         if (tried > 0 && budget_ms > 0.0 && spent >= budget_ms) continue;

@@ -141,3 +141,20 @@ def test_server_defaults_and_argument_errors():
     lib.apss_server_destroy(None)
     assert apss.strerror(apss.APSS_EBUSY) == "busy"
     assert apss.strerror(apss.APSS_PENDING) == "pending"
+
+
+def test_variant_3_is_refused():
+    """Variant 3 is withdrawn (refused before any device work), with or without the screen."""
+    import paper_1402_3010_amd as apss
+    lib = apss.load()
+    rp = np.array([0, 1], np.int64)
+    col = np.array([0], np.int32)
+    val = np.array([1.0], np.float32)
+    o = apss.default_opts(screen_dims=64, variant=3)
+    h = ctypes.c_void_p()
+    assert lib.apss_build_index(1, 4, rp.ctypes.data, col.ctypes.data, val.ctypes.data, 0, 0.5, ctypes.byref(o),
+                                ctypes.byref(h)) == apss.APSS_EINVAL
+    o = apss.default_opts(variant=3)
+    assert lib.apss_build_index(1, 4, rp.ctypes.data, col.ctypes.data, val.ctypes.data, 0, 0.5, ctypes.byref(o),
+                                ctypes.byref(h)) == apss.APSS_EINVAL
+    assert "not available" in apss.last_error()

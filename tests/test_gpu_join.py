@@ -270,7 +270,9 @@ def test_full_size_sampled(apss, name, t):
     assert st["matches"] == len(i)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, pytest.param(3, marks=pytest.mark.skip(
+    reason="variant 3 is withdrawn: it faulted the GPU (memory aperture violation) in two tuning runs on the "
+           "500k-vector workloads, cause not yet identified"))])
 def test_every_tile_variant(apss, variant):
     V = make_corpus(spec_for("c2", n=9000))
     t = np.float32(0.6)
