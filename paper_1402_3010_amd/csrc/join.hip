@@ -107,6 +107,7 @@ struct Smem {
   float qmw[C::QT];
   float qpn[C::QT];  // bound on the query's part in the corpus rows' unindexed dimensions
   float qt[C::QT];
+  float4 qb[C::QT];  // filter bounds of each query: threshold - slack, max weight, length * max weight, qpn
   int32_t qlen[C::QT];
   int32_t qhead[C::QT];
   int32_t wsum[C::NT / 64];
@@ -120,6 +121,12 @@ struct Smem {
   int64_t item;
   unsigned long long cnt[C_NUM];
 };
+
+// min of two non-negative finite floats (weights are validated positive):
+// their bit patterns order like the values, so one integer min does it
+__device__ __forceinline__ float min_nonneg(float x, float y) {
+  return __uint_as_float(min(__float_as_uint(x), __float_as_uint(y)));
+}
 
 template <class C>
 __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE))) void k_join(JoinArgs a) {
@@ -215,6 +222,13 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     const int64_t r0 = sm.qoff[tid], r1 = sm.qoff[tid + 1];
     sm.qlen[tid] = (int32_t)(r1 - r0);
     if (!staged) sm.qhead[tid] = find_head(a.qrc + r0, (int)(r1 - r0));
+  }
+  if (tid < QT) {
+    // slots past qn never hold a score, so their bounds are never used
+    // min(cut, len) * maxweight == min(cut * maxweight, len * maxweight) in
+    // float: rounding is monotone, so the per-row part needs one product
+    const int ql = tid < qn ? (int)(sm.qoff[tid + 1] - sm.qoff[tid]) : 0;
+    sm.qb[tid] = make_float4(sm.qt[tid] - kSlack, sm.qmw[tid], (float)ql * sm.qmw[tid], sm.qpn[tid]);
   }
   auto find_slot = [&](int64_t k) {
     int qi = 0;
@@ -518,11 +532,10 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             yst = r0;
             packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
             const float A = (float)av * kInvFix;
-            const float thr = sm.qt[qi] - kSlack;
-            const float qm = sm.qmw[qi];
-            const int ql = sm.qlen[qi];
-            const float mn = (float)(st.cut < ql ? st.cut : ql);
-            want = ((float)ylen * qm >= thr) && (A + mn * qm * st.pmw >= thr) && (A + sm.qpn[qi] * st.pnrm >= thr);
+            const float4 qb = sm.qb[qi];
+            const float thr = qb.x, qm = qb.y;
+            want = ((float)ylen * qm >= thr) && (A + min_nonneg((float)st.cut * qm, qb.z) * st.pmw >= thr) &&
+                   (A + qb.w * st.pnrm >= thr);
             ++c_cand;
           }
         }
@@ -823,44 +836,62 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         if (yi + 1 < YPT) load_rows(yi + 1);
         const int yl = yi * NT + tid;
         const int64_t y = blk0 + yl;
-        const bool yv = y < blk1;
+        // query slots qi >= qlo pair with this row: the triangle keeps the
+        // pairs whose corpus row precedes the query
+        int qlo = 0;
+        if (y >= blk1) {
+          qlo = QT;
+        } else if (a.triangle) {
+          const int64_t d = y - q0 + 1;
+          qlo = d <= 0 ? 0 : (d >= QT ? QT : (int)d);
+        }
         const uint32_t packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) |
                                 ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
+        const float ylf = (float)ylen, cutf = (float)st.cut;
         // slots beyond qn were never written and hold zeros
         uint32_t av[QT];
 #pragma unroll
         for (int qi = 0; qi < QT; ++qi) av[qi] = sm.acc[qi * CB + yl];
+        // the bounds of all slots first, without branches; the rare
+        // survivors are then queued slot by slot
+        uint32_t wbits = 0u, ncand = 0u;
 #pragma unroll
         for (int qi = 0; qi < QT; ++qi) {
-          bool want = false, retry = false;
-          if (av[qi] && yv && !(a.triangle && y >= q0 + qi)) {
-            const float A = (float)av[qi] * kInvFix;
-            const float thr = sm.qt[qi] - kSlack;
-            const float qm = sm.qmw[qi];
-            const int ql = sm.qlen[qi];
-            const float mn = (float)(st.cut < ql ? st.cut : ql);
-            want = ((float)ylen * qm >= thr) && (A + mn * qm * st.pmw >= thr) && (A + sm.qpn[qi] * st.pnrm >= thr);
-            ++c_cand;
-          }
-          const uint64_t wm = __ballot(want);
-          if (wm) {
-            int qb = 0;
-            if (lane == 0) qb = atomicAdd(&sm.qcount, (int)__popcll(wm));
-            qb = __shfl(qb, 0);
-            if (want) {
-              const int slot = qb + (int)__popcll(wm & lt);
-              if (slot < SQ) {
-                sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av[qi], yst, packed);
-                ++c_surv;
-              } else {
-                retry = true;  // queue full: keep the entry for the next pass
-                --c_cand;
-                sm.ovf = 1;
+          const float4 qb = sm.qb[qi];
+          const bool live = (av[qi] != 0u) & (qi >= qlo);
+          const float A = (float)av[qi] * kInvFix;
+          const bool want = live & (ylf * qb.y >= qb.x) & (A + min_nonneg(cutf * qb.y, qb.z) * st.pmw >= qb.x) &
+                            (A + qb.w * st.pnrm >= qb.x);
+          ncand += live ? 1u : 0u;
+          wbits |= want ? (1u << qi) : 0u;
+        }
+        uint32_t keep = 0u;  // queue full: these slots stay for the next pass
+        if (__ballot(wbits != 0u)) {
+#pragma unroll
+          for (int qi = 0; qi < QT; ++qi) {
+            const bool want = (wbits >> qi) & 1u;
+            const uint64_t wm = __ballot(want);
+            if (wm) {
+              int qb = 0;
+              if (lane == 0) qb = atomicAdd(&sm.qcount, (int)__popcll(wm));
+              qb = __shfl(qb, 0);
+              if (want) {
+                const int slot = qb + (int)__popcll(wm & lt);
+                if (slot < SQ) {
+                  sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av[qi], yst, packed);
+                  ++c_surv;
+                } else {
+                  keep |= 1u << qi;
+                  --ncand;
+                  sm.ovf = 1;
+                }
               }
             }
           }
-          if (av[qi] && !retry) sm.acc[qi * CB + yl] = 0u;
         }
+#pragma unroll
+        for (int qi = 0; qi < QT; ++qi) sm.acc[qi * CB + yl] = ((keep >> qi) & 1u) ? av[qi] : 0u;
+        c_cand += ncand;
       }
       __syncthreads();
       const int o = uni(sm.ovf);
