@@ -99,7 +99,10 @@ struct Smem {
   float qd[C::QT * C::RD];
   Seg seg[C::QB];
   int32_t segpre[C::QB + 1];
-  uint4 sq[C::SQ];  // x = slot << 16 | local y, y = fixed-point score (0 = dropped), z = row start, w = cut | len << 16
+  union {
+    uint4 sq[C::SQ];  // x = slot << 16 | local y, y = fixed-point score (0 = dropped), z = row start, w = cut | len << 16
+    uint32_t sflag[C::NT];  // segment-start flags of the short stream, 64 per wave (the queue is empty then)
+  };
   RComp qrow[C::QB];     // staged components of the tile
   uint2 cur[C::QB];      // list cursor of each staged component: {position, vector id at it}
   uint8_t cqi[C::QB];    // query slot of each staged component
@@ -121,6 +124,15 @@ struct Smem {
   int64_t item;
   unsigned long long cnt[C_NUM];
 };
+
+// Orders the LDS accesses of one wave around an exchange between its lanes
+// (LDS executes a wave's accesses in order; this keeps the compiler from
+// moving or forwarding them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // min of two non-negative finite floats (weights are validated positive):
 // their bit patterns order like the values, so one integer min does it
@@ -329,6 +341,13 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       else hi = mid - 1;
     }
     int sa = lo;  // segment holding the current chunk's first entry
+    // Each chunk of 64 entries flags, at chunk position s, every segment that
+    // starts there (segments are non-empty, so at most one per position);
+    // an entry's segment is sa plus the flags at or before it.  A flag holds
+    // the chunk's tag, so the flags of older chunks need no clearing.
+    uint32_t* const fl = sm.sflag + wave * 64;
+    fl[lane] = 0u;
+    uint32_t tag = 0u;
     for (int base = vbeg; base < vend; base += 64 * U) {
       uint32_t pos[U], qwb[U];
       int qs[U];
@@ -337,21 +356,22 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         const int c = base + u * 64;
         const int sj = sa + 1 + lane;
         const int rel = sj < ns ? sm.segpre[sj] - c : 0x7FFFFFFF;  // >= 1: segment sa holds entry c
-        int k = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-          const int r = __shfl(rel, k + step - 1, 64);
-          if (r <= lane) k += step;
-        }
+        ++tag;
+        if ((uint32_t)rel < 64u) fl[rel] = tag;
+        wave_lds_sync();
+        const bool f = fl[lane] == tag;
+        const uint64_t fm = __ballot(f);
+        const int k = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u)) +
+                      (f ? 1 : 0);
         const int sg = sa + k;
         const Seg S = sseg[sg];
         const int v = c + lane;
         pos[u] = S.pos + (uint32_t)(v - sm.segpre[sg]);
         qwb[u] = S.q;
         qs[u] = v < vend ? (int)(S.lenq >> 16) : -1;
-        // the next chunk starts in the last entry's segment or the one after
-        const int last = __shfl(sg, 63, 64);
-        sa = (last + 1 < ns && sm.segpre[last + 1] <= c + 64) ? last + 1 : last;
+        // the next chunk starts in the segment holding entry c + 64
+        sa += (int)__popcll(__ballot(rel <= 64));
+        wave_lds_sync();
       }
       uint32_t pv[U];
 #pragma unroll
