@@ -242,7 +242,7 @@ int build_lists(apss_index* ix) {
   CHK(hipMemcpyAsync(&P, total.p, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read P");
   CHK(hipStreamSynchronize(s), "read P");
   ix->P = P;
-  if (4 * (P + 1) >= (1ll << 32)) {
+  if (4 * (P + kPost4Pad) >= (1ll << 32)) {
     set_error("index too large: %lld postings (the packed lists must stay below 4 GiB)", (long long)P);
     return APSS_EINVAL;
   }
@@ -266,7 +266,11 @@ int build_lists(apss_index* ix) {
   CHK(ix->post.alloc(P + 1), "alloc");
   CHK(fill_u64((uint64_t*)ix->post.p + P, ~0ull, 1, s), "fill");
   CHK(launch_unpack_post(ss.v64a.p, P, ix->post.p, s), "post");
-  CHK(ix->post4.alloc(P + 1), "alloc");
+  // the join's list loads put a chunk's base in the scalar offset, which the
+  // hardware range check does not cover: 64 zero entries after the last list
+  // keep a chunk's lanes past its end inside the allocation
+  CHK(ix->post4.alloc(P + kPost4Pad), "alloc");
+  CHK(fill_u32(ix->post4.p + P, 0u, kPost4Pad, s), "fill");
   CHK(launch_pack_post4(ix->post.p, P, ix->post4.p, s), "post4");
 
   // per-block offsets of the dense lists, for the default tile variant
@@ -457,7 +461,7 @@ int plan_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, fl
   a.off = ix->off.p;
   a.post = ix->post.p;
   a.post4 = ix->post4.p;
-  a.post4_bytes = (uint32_t)(4 * (ix->P + 1));
+  a.post4_bytes = (uint32_t)(4 * (ix->P + kPost4Pad));
   a.hoff = ix->hoff[slot].p;
   a.H = ix->H;
   a.nb = nb;

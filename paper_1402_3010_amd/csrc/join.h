@@ -5,6 +5,10 @@
 
 namespace apss {
 
+// zero entries after the last list of the packed list array: a list chunk's
+// lanes past its end stay inside the allocation
+constexpr int64_t kPost4Pad = 64;
+
 struct JoinArgs {
   // corpus index
   const int64_t* rp;      // [n+1] row offsets of the rank-space rows
@@ -12,7 +16,7 @@ struct JoinArgs {
   const RowStat* rs;      // [n]
   const int64_t* off;     // [m+1] list offsets by rank
   const Post* post;       // [P]   list entries, vector ids ascending within a list
-  const uint32_t* post4;  // [P+1] the same entries packed: id mod 2^16 | weight in 2^-15 units (rounded up) << 16
+  const uint32_t* post4;  // [P+kPost4Pad] the same entries packed: id mod 2^16 | weight in 2^-15 units (rounded up) << 16
   uint32_t post4_bytes;   // size of post4 in bytes (< 2^32)
   const uint32_t* hoff;   // [(nb+1) * H] first entry of list r at or after block b
   int32_t H;              // ranks with block offsets

@@ -155,7 +155,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   unsigned long long c_visit = 0, c_tail = 0, c_cand = 0, c_surv = 0, c_ver = 0, c_band = 0;
-  uint64_t vis_u = 0;  // visits of long segments, counted per wave (uniform)
   if (tid < C_NUM) sm.cnt[tid] = 0;
   const __amdgpu_buffer_rsrc_t prs = make_rsrc(a.post4, a.post4_bytes);
   // the accumulators start at zero and every item leaves them at zero
@@ -773,73 +772,86 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw) {
         atomicAdd(&sm.acc[qi * CB + (int)(p & (CB - 1))], packed_product(qw, p));
       });
-      // long segments: wave w walks segments w, w + NW, ... in chunks of 64
-      // entries (one entry per lane) with all bookkeeping uniform.  Two
+      // long segments: wave w takes segments w, w + NW, ... in chunks of 64
+      // entries (one per lane).  Lane i holds the descriptor of the wave's
+      // segment i (64 at a time), which the walk reads with readlane: the
+      // bookkeeping stays in scalar registers and needs no LDS access.  Two
       // batches of UL chunks alternate: the next batch's loads are issued
       // before the current batch is accumulated, so loads stay in flight.
       {
-        int si = wave, off = 0;
-        uint32_t spos = 0, slenq = 0, sq = 0;
-        int cur_si = -1;
-        // next UL chunks of this wave's segments (uniform values)
-        auto gather = [&](uint32_t (&cpos)[UL], uint32_t (&cq)[UL], int (&ccnt)[UL], int (&cab)[UL]) {
+        const int nwl = nl > wave ? (nl - wave + NW - 1) / NW : 0;  // this wave's segments
+        uint32_t dpos = 0u, dab = 0u, dq = 0u;  // lane i: segment j0 + i (byte offset, acc row, weight)
+        int dlen = 0;
+        auto load_desc = [&](int j0) {
+          dlen = 0;
+          if (j0 + lane < nwl) {
+            const Seg S = sm.seg[wave + (j0 + lane) * NW];
+            dpos = S.pos * 4u;
+            dlen = (int)(S.lenq & 0xFFFFu);
+            dab = (S.lenq >> 16) * (uint32_t)CB;
+            dq = S.q;
+            c_visit += (unsigned long long)dlen;
+          }
+        };
+        int j = 0;     // segment being handed out
+        int left = 0;  // its entries not yet handed out (<= 0: the wave is done)
+        uint32_t soff = 0u, sab = 0u, sq = 0u;
+        auto take = [&]() {  // j < nwl
+          if ((j & 63) == 0) load_desc(j);
+          const int l = j & 63;
+          soff = (uint32_t)__builtin_amdgcn_readlane((int)dpos, l);
+          left = __builtin_amdgcn_readlane(dlen, l);
+          sab = (uint32_t)__builtin_amdgcn_readlane((int)dab, l);
+          sq = (uint32_t)__builtin_amdgcn_readlane((int)dq, l);
+        };
+        if (nwl > 0) take();
+        // next UL chunks (uniform values); chunks past the end have no entries
+        auto gather = [&](uint32_t (&coff)[UL], uint32_t (&cq)[UL], int (&ccnt)[UL], uint32_t (&cab)[UL]) {
 #pragma unroll
           for (int u = 0; u < UL; ++u) {
-            ccnt[u] = 0;
-            cpos[u] = 0;
-            cab[u] = 0;
-            cq[u] = 0;
-            if (si < nl) {
-              if (si != cur_si) {
-                const Seg S = sm.seg[si];
-                spos = __builtin_amdgcn_readfirstlane(S.pos);
-                slenq = __builtin_amdgcn_readfirstlane(S.lenq);
-                sq = __builtin_amdgcn_readfirstlane(S.q);
-                cur_si = si;
-              }
-              const int len = (int)(slenq & 0xFFFFu);
-              const int left = len - off;
-              ccnt[u] = left < 64 ? left : 64;
-              cpos[u] = spos + (uint32_t)off;
-              cab[u] = (int)(slenq >> 16) * CB;
-              cq[u] = sq;
-              off += 64;
-              if (off >= len) {
-                off = 0;
-                si += NW;
-              }
+            ccnt[u] = left < 64 ? left : 64;
+            coff[u] = left > 0 ? soff : 0u;
+            cab[u] = sab;
+            cq[u] = sq;
+            soff += 256u;
+            left -= 64;
+            if (left <= 0 && j + 1 < nwl) {
+              ++j;
+              take();
             }
           }
         };
         // one buffer load per chunk: scalar base, lane offset; lanes past the
-        // chunk read other entries (or zeros past the array) and are masked
-        auto issue = [&](uint32_t (&p)[UL], const uint32_t (&cpos)[UL]) {
+        // chunk read other entries, or the zero padding after the last list
+        auto issue = [&](uint32_t (&p)[UL], const uint32_t (&coff)[UL]) {
 #pragma unroll
-          for (int u = 0; u < UL; ++u)
-            p[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, lane * 4, (int)(cpos[u] * 4u), 0);
+          for (int u = 0; u < UL; ++u) p[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, lane * 4, (int)coff[u], 0);
         };
+        // lanes past the chunk add zero to a slot of the same accumulator row
         auto consume = [&](const uint32_t (&p)[UL], const uint32_t (&cq)[UL], const int (&ccnt)[UL],
-                           const int (&cab)[UL]) {
+                           const uint32_t (&cab)[UL]) {
 #pragma unroll
           for (int u = 0; u < UL; ++u) {
-            if (ccnt[u] > 0) {
-              vis_u += (uint32_t)ccnt[u];
-              if (lane < ccnt[u]) atomicAdd(&sm.acc[cab[u] + (int)(p[u] & (CB - 1))], packed_product(cq[u], p[u]));
-            }
+            const uint32_t w = lane < ccnt[u] ? packed_product(cq[u], p[u]) : 0u;
+            atomicAdd(&sm.acc[cab[u] + (p[u] & (uint32_t)(CB - 1))], w);
           }
         };
-        uint32_t apos[UL], aq[UL], pa[UL], bpos[UL], bq[UL], pb[UL];
-        int acnt[UL], aab[UL], bcnt[UL], bab[UL];
-        gather(apos, aq, acnt, aab);
-        issue(pa, apos);
+        uint32_t aoff[UL], aq[UL], pa[UL], boff[UL], bq[UL], pb[UL], aab[UL], bab[UL];
+        int acnt[UL], bcnt[UL];
+        gather(aoff, aq, acnt, aab);
+        issue(pa, aoff);
+        // (the scheduling barriers keep each batch's loads ahead of the
+        // other batch's accumulation)
         for (;;) {
           if (acnt[0] <= 0) break;
-          gather(bpos, bq, bcnt, bab);
-          issue(pb, bpos);
+          gather(boff, bq, bcnt, bab);
+          issue(pb, boff);
+          __builtin_amdgcn_sched_barrier(0);
           consume(pa, aq, acnt, aab);
           if (bcnt[0] <= 0) break;
-          gather(apos, aq, acnt, aab);
-          issue(pa, apos);
+          gather(aoff, aq, acnt, aab);
+          issue(pa, aoff);
+          __builtin_amdgcn_sched_barrier(0);
           consume(pb, bq, bcnt, bab);
         }
       }
@@ -928,7 +940,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 
   // ------------------------------------------------------------ counters
   __syncthreads();
-  if (lane == 0) c_visit += vis_u;
   atomicAdd(&sm.cnt[C_VISITS], c_visit);
   atomicAdd(&sm.cnt[C_TAILVISITS], c_tail);
   atomicAdd(&sm.cnt[C_CANDIDATES], c_cand);
