@@ -110,7 +110,7 @@ struct Smem {
   float qmw[C::QT];
   float qpn[C::QT];  // bound on the query's part in the corpus rows' unindexed dimensions
   float qt[C::QT];
-  float4 qb[C::QT];  // filter bounds of each query: threshold - slack, max weight, length * max weight, qpn
+  float4 qb[C::QT];  // filter bounds of each query, times 2^30: threshold - slack, max weight, length * max weight, qpn
   int32_t qlen[C::QT];
   int32_t qhead[C::QT];
   int32_t wsum[C::NT / 64];
@@ -238,12 +238,19 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     // slots past qn never hold a score, so their bounds are never used
     // min(cut, len) * maxweight == min(cut * maxweight, len * maxweight) in
     // float: rounding is monotone, so the per-row part needs one product
+    // The bounds are kept in accumulator units (2^30 per unit of score):
+    // scaling by a power of two commutes with float rounding, so comparing
+    // the raw accumulator with them decides exactly as in score units.
     const int ql = tid < qn ? (int)(sm.qoff[tid + 1] - sm.qoff[tid]) : 0;
-    sm.qb[tid] = make_float4(sm.qt[tid] - kSlack, sm.qmw[tid], (float)ql * sm.qmw[tid], sm.qpn[tid]);
+    sm.qb[tid] = make_float4((sm.qt[tid] - kSlack) * kFix, sm.qmw[tid] * kFix, (float)ql * sm.qmw[tid] * kFix,
+                             sm.qpn[tid] * kFix);
   }
+  // query slot of tile component k: the last qi with qoff[qi] <= k
   auto find_slot = [&](int64_t k) {
     int qi = 0;
-    while (qi + 1 < qn && sm.qoff[qi + 1] <= k) ++qi;
+#pragma unroll
+    for (int step = QT / 2; step >= 1; step >>= 1)
+      if (qi + step < qn && sm.qoff[qi + step] <= k) qi += step;
     return qi;
   };
   int64_t last_b = -1;
@@ -323,10 +330,10 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   // their lengths in sm.segpre, L entries in all): wave w takes a contiguous
   // slice, 64 consecutive entries per load (lane l, entry c + l), U loads in
   // flight per lane.  The segment of each entry: lane j holds the start of
-  // the j-th segment after the one holding the chunk's first entry (starts
-  // increase with j), and every lane counts the starts at or before its own
-  // entry by a binary search over the lanes (six shuffles).  Segments are
-  // never empty, so at most 63 of them start inside a chunk.
+  // the j-th segment after the one holding the chunk's first entry, flags
+  // that start in a per-wave LDS row, and every lane counts the flags at or
+  // before its own entry (one ballot).  Segments are never empty, so at most
+  // 63 of them start inside a chunk.
   // add(qi, packed entry, query weight).
   auto stream_short = [&](const Seg* sseg, int ns, int L, auto&& add) {
     const int per = (((L + NW - 1) / NW) + 63) & ~63;
@@ -550,7 +557,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             const int ylen = (int)((uint32_t)a.rp[y + 1] - r0);
             yst = r0;
             packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
-            const float A = (float)av * kInvFix;
+            const float A = (float)av;  // accumulator units, as the bounds
             const float4 qb = sm.qb[qi];
             const float thr = qb.x, qm = qb.y;
             want = ((float)ylen * qm >= thr) && (A + min_nonneg((float)st.cut * qm, qb.z) * st.pmw >= thr) &&
@@ -627,7 +634,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       // block offsets; sparse lists with an entry in this block get their
       // first two entries loaded (no waiting here)
       bool thit[KMAX];
-      Post t0[KMAX], t1[KMAX];
+      Post t0[KMAX];
+      uint32_t t1y[KMAX];
+      uint32_t hq[KMAX];  // byte offset of the next block's segment end in hnext (out of range: none)
       uint32_t tpos[KMAX], tend[KMAX];
       float tw[KMAX];
       int tqi[KMAX];
@@ -637,6 +646,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         bool has_seg = false;
         Seg sg = {0u, 0u, 0u};
         thit[j] = false;
+        hq[j] = 0xFFFFFFFFu;
         tpos[j] = 0;
         tend[j] = 0;
         tw[j] = 0.0f;
@@ -663,7 +673,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             uint32_t e;
             if (staged) {
               e = hn[j];
-              if (b + 1 < b_end) hn[j] = hnext[c.r];  // prefetch for the next block
+              hq[j] = (uint32_t)c.r * 4u;  // prefetched below for the next block
             } else {
               e = hend[c.r];
             }
@@ -682,7 +692,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             tqi[j] = qi;
             tend[j] = (uint32_t)a.off[c.r + 1];
             t0[j] = a.post[pos];
-            t1[j] = a.post[pos + 1];  // the list array carries one padding entry
+            t1y[j] = a.post[pos + 1].y;  // the list array carries one padding entry
           }
         }
         // long segments go to the front (one wave each), short ones to the
@@ -701,6 +711,14 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         if (is_long) sm.seg[lb + (int)__popcll(ml & lt)] = sg;
         if (is_short) sm.seg[QB - 1 - (sb + (int)__popcll(msh & lt))] = sg;
       }
+      // the dense lists' segment ends of the next block, for staged tiles:
+      // unconditional buffer loads (a component with none reads out of
+      // range, which returns 0), so nothing waits on them before that block
+      if (staged) {
+        const __amdgpu_buffer_rsrc_t hrs = make_rsrc(hnext, b + 1 < b_end ? (uint32_t)a.H * 4u : 0u);
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) hn[j] = __builtin_amdgcn_raw_buffer_load_b32(hrs, (int)hq[j], 0, 0);
+      }
       // pass 2: sparse lists, usually one entry per block
 #pragma unroll
       for (int j = 0; j < KMAX; ++j) {
@@ -712,7 +730,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           atomicAdd(&sm.acc[ab + (int)t0[j].y], fixp(tw[j], t0[j].w));
           ++c_tail;
           ++pos;
-          uint32_t ny = pos < end ? t1[j].y : 0xFFFFFFFFu;
+          uint32_t ny = pos < end ? t1y[j] : 0xFFFFFFFFu;
           while ((int64_t)ny < blk1) {
             const Post p = a.post[pos];
             atomicAdd(&sm.acc[ab + (int)p.y], fixp(tw[j], p.w));
@@ -891,7 +909,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         for (int qi = 0; qi < QT; ++qi) {
           const float4 qb = sm.qb[qi];
           const bool live = (av[qi] != 0u) & (qi >= qlo);
-          const float A = (float)av[qi] * kInvFix;
+          const float A = (float)av[qi];  // accumulator units, as the bounds
           const bool want = live & (ylf * qb.y >= qb.x) & (A + min_nonneg(cutf * qb.y, qb.z) * st.pmw >= qb.x) &
                             (A + qb.w * st.pnrm >= qb.x);
           ncand += live ? 1u : 0u;
