@@ -101,7 +101,10 @@ struct Smem {
   int32_t segpre[C::QB + 1];
   union {
     uint4 sq[C::SQ];  // x = slot << 16 | local y, y = fixed-point score (0 = dropped), z = row start, w = cut | len << 16
-    uint32_t sflag[C::NT];  // segment-start flags of the short stream, 64 per wave (the queue is empty then)
+    struct {  // the short stream's tables (the survivor queue is empty then)
+      uint8_t flag[C::NT / 64][C::U][64];  // segment-start flags: one row per wave and chunk of a batch
+      uint16_t first[C::QB * (kLongSeg - 1) / 64 + 2];  // segment holding each 64-entry chunk's first entry
+    } ss;
   };
   RComp qrow[C::QB];     // staged components of the tile
   uint2 cur[C::QB];      // list cursor of each staged component: {position, vector id at it}
@@ -148,6 +151,10 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   constexpr int YPT = CB / NT;   // corpus rows per thread in the filter
   static_assert(KMAX >= 1 && QB % NT == 0 && CB % NT == 0, "tile geometry");
   static_assert(CB <= 65536 && QT <= 256, "survivor packing");
+  // the short stream's chunk table covers a hashed item's entries (at most
+  // 3/4 of the table size) and its per-batch tags fit a byte
+  static_assert((QT * CB / 2) * 3 / 4 / 64 + 1 <= QB * (kLongSeg - 1) / 64 + 2, "chunk table");
+  static_assert((QB * (kLongSeg - 1) / NW + 64) / (64 * U) + 2 < 255, "stream tags");
   __shared__ Smem<C> sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -335,50 +342,93 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   // before its own entry (one ballot).  Segments are never empty, so at most
   // 63 of them start inside a chunk.
   // add(qi, packed entry, query weight).
+  // Exclusive prefix sums of the lengths of sseg[0..ns) into sm.segpre (KMAX
+  // consecutive segments per thread), and for every 64-entry chunk of the
+  // concatenated segments the segment that holds its first entry.  Ends
+  // with the writes pending: the caller synchronises.
+  auto scan_short = [&](const Seg* sseg, int ns) {
+    int loc[KMAX], len[KMAX];
+    int run = 0;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      const int e = tid * KMAX + j;
+      loc[j] = run;
+      len[j] = e < ns ? (int)(sseg[e].lenq & 0xFFFFu) : 0;
+      run += len[j];
+    }
+    int incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += u;
+    }
+    if (lane == 63) sm.wsum[wave] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int w = 0; w < wave; ++w) woff += sm.wsum[w];
+    const int excl = woff + incl - run;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      const int e = tid * KMAX + j;
+      if (e < ns) {
+        const int s0 = excl + loc[j];
+        sm.segpre[e] = s0;
+        for (int c = (s0 + 63) & ~63; c < s0 + len[j]; c += 64) sm.ss.first[c >> 6] = (uint16_t)e;
+      }
+    }
+    if (tid == NT - 1) sm.segpre[ns] = woff + incl;
+  };
+
+  // Every entry of the short segments sseg[0..ns) (exclusive prefix sums of
+  // their lengths in sm.segpre, L entries in all, chunk table from
+  // scan_short): wave w takes a contiguous slice of whole 64-entry chunks, U
+  // chunks per batch (lane l, entry c + l), U loads in flight per lane.  The
+  // segment of each entry: the chunk table gives the segment sa holding the
+  // chunk's first entry; lane j takes the start of segment sa + 1 + j and
+  // flags it in the chunk's LDS row; every lane counts the flags at or before
+  // its own entry (one ballot).  Segments are never empty, so at most 63 of
+  // them start inside a chunk.  A flag holds the batch's tag, so older flags
+  // need no clearing.  The chunks of a batch are independent, so their LDS
+  // round trips overlap.  add(qi, packed entry, query weight).
   auto stream_short = [&](const Seg* sseg, int ns, int L, auto&& add) {
     const int per = (((L + NW - 1) / NW) + 63) & ~63;
     const int vbeg = wave * per;
     const int vend = (vbeg + per) < L ? (vbeg + per) : L;
     if (vbeg >= vend) return;
-    int lo = 0, hi = ns - 1;  // segment holding entry vbeg
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (sm.segpre[mid] <= vbeg) lo = mid;
-      else hi = mid - 1;
-    }
-    int sa = lo;  // segment holding the current chunk's first entry
-    // Each chunk of 64 entries flags, at chunk position s, every segment that
-    // starts there (segments are non-empty, so at most one per position);
-    // an entry's segment is sa plus the flags at or before it.  A flag holds
-    // the chunk's tag, so the flags of older chunks need no clearing.
-    uint32_t* const fl = sm.sflag + wave * 64;
-    fl[lane] = 0u;
+#pragma unroll
+    for (int u = 0; u < U; ++u) sm.ss.flag[wave][u][lane] = 0;
     uint32_t tag = 0u;
     for (int base = vbeg; base < vend; base += 64 * U) {
+      ++tag;
+      int sa[U], rel[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = base + u * 64;
+        sa[u] = c < vend ? (int)sm.ss.first[c >> 6] : 0;
+        const int sj = sa[u] + 1 + lane;
+        rel[u] = (c < vend && sj < ns) ? sm.segpre[sj] - c : 0x7FFFFFFF;  // >= 1: segment sa holds entry c
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if ((uint32_t)rel[u] < 64u) sm.ss.flag[wave][u][rel[u]] = (uint8_t)tag;
+      wave_lds_sync();
       uint32_t pos[U], qwb[U];
       int qs[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int c = base + u * 64;
-        const int sj = sa + 1 + lane;
-        const int rel = sj < ns ? sm.segpre[sj] - c : 0x7FFFFFFF;  // >= 1: segment sa holds entry c
-        ++tag;
-        if ((uint32_t)rel < 64u) fl[rel] = tag;
-        wave_lds_sync();
-        const bool f = fl[lane] == tag;
+        const bool f = sm.ss.flag[wave][u][lane] == (uint8_t)tag;
         const uint64_t fm = __ballot(f);
         const int k = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u)) +
                       (f ? 1 : 0);
-        const int sg = sa + k;
+        const int sg = sa[u] + k;
         const Seg S = sseg[sg];
         const int v = c + lane;
         pos[u] = S.pos + (uint32_t)(v - sm.segpre[sg]);
         qwb[u] = S.q;
         qs[u] = v < vend ? (int)(S.lenq >> 16) : -1;
-        // the next chunk starts in the segment holding entry c + 64
-        sa += (int)__popcll(__ballot(rel <= 64));
-        wave_lds_sync();
       }
+      wave_lds_sync();
       uint32_t pv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) pv[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, (int)(pos[u] * 4u), 0, 0);
@@ -491,33 +541,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     // the live segments written at staging, contiguous at the back of seg[]
     const int ns = uni(sm.nshort);
     Seg* const sseg = sm.seg + (QB - ns);
-    {
-      int loc[KMAX];
-      int run = 0;
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j) {
-        const int e = tid * KMAX + j;
-        loc[j] = run;
-        run += e < ns ? (int)(sseg[e].lenq & 0xFFFFu) : 0;
-      }
-      int incl = run;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += u;
-      }
-      if (lane == 63) sm.wsum[wave] = incl;
-      __syncthreads();
-      int woff = 0;
-      for (int w = 0; w < wave; ++w) woff += sm.wsum[w];
-      const int excl = woff + incl - run;
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j) {
-        const int e = tid * KMAX + j;
-        if (e < ns) sm.segpre[e] = excl + loc[j];
-      }
-      if (tid == NT - 1) sm.segpre[ns] = woff + incl;
-    }
+    scan_short(sseg, ns);
     __syncthreads();
     const int L = uni(sm.segpre[ns]);
     if (tid == 0) c_visit += (unsigned long long)L;
@@ -750,34 +774,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       const int nl = uni(sm.nseg);
       const int ns = uni(sm.nshort);
       Seg* const sseg = sm.seg + (QB - ns);  // the short segments, contiguous
-      // exclusive scan of the short segments' lengths (KMAX consecutive entries per thread)
-      {
-        int loc[KMAX];
-        int run = 0;
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j) {
-          const int e = tid * KMAX + j;
-          loc[j] = run;
-          run += e < ns ? (int)(sseg[e].lenq & 0xFFFFu) : 0;
-        }
-        int incl = run;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int u = __shfl_up(incl, o, 64);
-          if (lane >= o) incl += u;
-        }
-        if (lane == 63) sm.wsum[wave] = incl;
-        __syncthreads();
-        int woff = 0;
-        for (int w = 0; w < wave; ++w) woff += sm.wsum[w];
-        const int excl = woff + incl - run;
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j) {
-          const int e = tid * KMAX + j;
-          if (e < ns) sm.segpre[e] = excl + loc[j];
-        }
-        if (tid == NT - 1) sm.segpre[ns] = woff + incl;
-      }
+      scan_short(sseg, ns);
       __syncthreads();
       const int L = uni(sm.segpre[ns]);
       if (tid == 0) {
