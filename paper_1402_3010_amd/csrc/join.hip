@@ -99,13 +99,15 @@ struct Smem {
   float qd[C::QT * C::RD];
   Seg seg[C::QB];
   int32_t segpre[C::QB + 1];
-  union {
-    uint4 sq[C::SQ];  // x = slot << 16 | local y, y = fixed-point score (0 = dropped), z = row start, w = cut | len << 16
-    struct {  // the short stream's tables (the survivor queue is empty then)
-      uint8_t flag[C::NT / 64][C::U][64];  // segment-start flags: one row per wave and chunk of a batch
-      uint16_t first[C::QB * (kLongSeg - 1) / 64 + 2];  // segment holding each 64-entry chunk's first entry
-    } ss;
+  // the short stream's tables
+  struct ShortTables {
+    uint8_t flag[C::NT / 64][C::U][64];  // segment-start flags: one row per wave and chunk of a batch
+    uint16_t first[C::QB * (kLongSeg - 1) / 64 + 2];  // segment holding each 64-entry chunk's first entry
   };
+  // survivor queue entries: the configured capacity less the tables' room
+  static constexpr int SQE = C::SQ - (int)((sizeof(ShortTables) + 15) / 16);
+  uint4 sq[SQE];  // x = slot << 16 | y - dbase, y = fixed-point score (0 = dropped), z = row start, w = cut | len << 16
+  ShortTables ss;
   RComp qrow[C::QB];     // staged components of the tile
   uint2 cur[C::QB];      // list cursor of each staged component: {position, vector id at it}
   uint8_t cqi[C::QB];    // query slot of each staged component
@@ -145,12 +147,13 @@ __device__ __forceinline__ float min_nonneg(float x, float y) {
 
 template <class C>
 __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE))) void k_join(JoinArgs a) {
-  constexpr int QT = C::QT, CB = C::CB, NT = C::NT, RD = C::RD, SQ = C::SQ, QB = C::QB, U = C::U, UL = C::UL;
+  constexpr int QT = C::QT, CB = C::CB, NT = C::NT, RD = C::RD, SQ = Smem<C>::SQE, QB = C::QB, U = C::U, UL = C::UL;
   constexpr int NW = NT / 64;
   constexpr int KMAX = QB / NT;  // staged components per thread
   constexpr int YPT = CB / NT;   // corpus rows per thread in the filter
   static_assert(KMAX >= 1 && QB % NT == 0 && CB % NT == 0, "tile geometry");
   static_assert(CB <= 65536 && QT <= 256, "survivor packing");
+  static_assert(SQ >= 128, "survivor queue");
   // the short stream's chunk table covers a hashed item's entries (at most
   // 3/4 of the table size) and its per-batch tags fit a byte
   static_assert((QT * CB / 2) * 3 / 4 / 64 + 1 <= QB * (kLongSeg - 1) / 64 + 2, "chunk table");
@@ -632,9 +635,14 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     }
     __syncthreads();
   }
+  // Survivors of several blocks share the queue (their rows named from the
+  // item's first row) when the item's rows fit the 16-bit offset; the queue
+  // is drained when half full, on overflow and after the item's last block.
+  const bool defer = (int64_t)a.K * CB <= 65536;
   for (int64_t b = (hashed ? b_end : b_begin); b < b_end; ++b) {
     const int64_t blk0 = b * CB;
-    dbase = blk0;
+    dbase = defer ? b_begin * CB : blk0;
+    const uint32_t yoff = (uint32_t)(blk0 - dbase);  // queue offset of the block's first row
     const int64_t blk1 = (blk0 + CB) < a.n ? (blk0 + CB) : a.n;
     const uint32_t* hend = a.hoff + (b + 1) * (int64_t)a.H;   // end of each dense list's block segment
     const uint32_t* hnext = a.hoff + (b + 2) * (int64_t)a.H;  // same for the next block (b < last_b)
@@ -925,7 +933,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
               if (want) {
                 const int slot = qb + (int)__popcll(wm & lt);
                 if (slot < SQ) {
-                  sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av[qi], yst, packed);
+                  sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (yoff + (uint32_t)yl), av[qi], yst, packed);
                   ++c_surv;
                 } else {
                   keep |= 1u << qi;
@@ -944,7 +952,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       const int o = uni(sm.ovf);
       const int qc = uni(sm.qcount);
       __syncthreads();
-      if (qc > 0) drain();
+      if (qc > 0 && (o || !defer || b + 1 == b_end || qc >= SQ / 2)) drain();
       if (!o) break;
     }
   }
