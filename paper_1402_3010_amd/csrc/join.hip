@@ -119,9 +119,8 @@ struct Smem {
   int32_t qlen[C::QT];
   int32_t qhead[C::QT];
   int32_t wsum[C::NT / 64];
-  int32_t nseg;    // long segments, stored from the front of seg[]
-  int32_t nshort;  // short segments, stored from the back of seg[]
-  int32_t lnext;   // next long segment to hand out
+  uint2 wsum2[C::NT / 64];  // per-wave totals of the block path's segment allocation
+  int32_t nshort;  // staged segments of a hashed item, stored from the back of seg[]
   int32_t qcount;
   int32_t ovf;
   int32_t vtot;    // list entries of the tile in the item's range (staged tiles)
@@ -216,9 +215,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     sm.qt[tid] = (tid < qn && a.qt) ? a.qt[q0 + tid] : a.t;
   }
   if (tid == 0) {
-    sm.nseg = 0;
     sm.nshort = 0;
-    sm.lnext = 0;
     sm.qcount = 0;
     sm.ovf = 0;
     sm.vtot = 0;
@@ -626,7 +623,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   if (!hashed && b_begin < b_end) {
     // the block path builds its own segments, and walks the sparse lists
     // from the vector id of their first entry in the range
-    if (tid == 0) sm.nshort = 0;
     if (staged) {
       for (int64_t k = tid; k < tile_nnz; k += NT) {
         const uint2 cu = sm.cur[k];
@@ -666,6 +662,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       // block offsets; sparse lists with an entry in this block get their
       // first two entries loaded (no waiting here)
       bool thit[KMAX];
+      Seg sgj[KMAX];  // this thread's segment of each component, placed after the allocation scan
+      int sk[KMAX];   // its kind: 0 none, 1 short, 2 long
       Post t0[KMAX];
       uint32_t t1y[KMAX];
       uint32_t hq[KMAX];  // byte offset of the next block's segment end in hnext (out of range: none)
@@ -727,21 +725,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             t1y[j] = a.post[pos + 1].y;  // the list array carries one padding entry
           }
         }
-        // long segments go to the front (one wave each), short ones to the
-        // back (split evenly over all lanes)
-        const bool is_long = has_seg && (sg.lenq & 0xFFFFu) >= (uint32_t)kLongSeg;
-        const bool is_short = has_seg && !is_long;
-        const uint64_t ml = __ballot(is_long);
-        const uint64_t msh = __ballot(is_short);
-        int lb = 0, sb = 0;
-        if (lane == 0) {
-          if (ml) lb = atomicAdd(&sm.nseg, (int)__popcll(ml));
-          if (msh) sb = atomicAdd(&sm.nshort, (int)__popcll(msh));
-        }
-        lb = __shfl(lb, 0);
-        sb = __shfl(sb, 0);
-        if (is_long) sm.seg[lb + (int)__popcll(ml & lt)] = sg;
-        if (is_short) sm.seg[QB - 1 - (sb + (int)__popcll(msh & lt))] = sg;
+        sgj[j] = sg;
+        sk[j] = !has_seg ? 0 : ((sg.lenq & 0xFFFFu) >= (uint32_t)kLongSeg ? 2 : 1);
       }
       // the dense lists' segment ends of the next block, for staged tiles:
       // unconditional buffer loads (a component with none reads out of
@@ -778,18 +763,65 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           }
         }
       }
-      __syncthreads();
-      const int nl = uni(sm.nseg);
-      const int ns = uni(sm.nshort);
-      Seg* const sseg = sm.seg + (QB - ns);  // the short segments, contiguous
-      scan_short(sseg, ns);
-      __syncthreads();
-      const int L = uni(sm.segpre[ns]);
-      if (tid == 0) {
-        c_visit += (unsigned long long)L;
-        sm.nseg = 0;
-        sm.nshort = 0;
+      // Allocation: an exclusive scan over the threads of (long segments,
+      // short segments, short entries) places long segments at the front of
+      // seg[] (one wave each) and short ones, in thread order, at the back
+      // (split evenly over all lanes), with their entry prefix sums and the
+      // chunk table of the short stream.
+      int nl, ns, L;
+      Seg* sseg;
+      {
+        uint32_t cnt = 0u, len = 0u;  // long << 16 | short, short entries
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+          cnt += sk[j] == 2 ? 0x10000u : (sk[j] == 1 ? 1u : 0u);
+          len += sk[j] == 1 ? (sgj[j].lenq & 0xFFFFu) : 0u;
+        }
+        uint32_t icnt = cnt, ilen = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t uc = __shfl_up(icnt, o, 64);
+          const uint32_t ul = __shfl_up(ilen, o, 64);
+          if (lane >= o) {
+            icnt += uc;
+            ilen += ul;
+          }
+        }
+        if (lane == 63) sm.wsum2[wave] = make_uint2(icnt, ilen);
+        __syncthreads();
+        uint32_t wc = 0u, wl = 0u, tc = 0u, tl = 0u;  // earlier waves, all waves
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const uint2 v = sm.wsum2[w];
+          if (w < wave) {
+            wc += v.x;
+            wl += v.y;
+          }
+          tc += v.x;
+          tl += v.y;
+        }
+        nl = (int)(tc >> 16);
+        ns = (int)(tc & 0xFFFFu);
+        L = (int)tl;
+        sseg = sm.seg + (QB - ns);
+        const uint32_t ec = wc + icnt - cnt;
+        int lb = (int)(ec >> 16), sb = (int)(ec & 0xFFFFu), lp = (int)(wl + ilen - len);
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+          if (sk[j] == 2) sm.seg[lb++] = sgj[j];
+          if (sk[j] == 1) {
+            const int sl = (int)(sgj[j].lenq & 0xFFFFu);
+            sseg[sb] = sgj[j];
+            sm.segpre[sb] = lp;
+            for (int c = (lp + 63) & ~63; c < lp + sl; c += 64) sm.ss.first[c >> 6] = (uint16_t)sb;
+            ++sb;
+            lp += sl;
+          }
+        }
+        if (tid == 0) sm.segpre[ns] = L;
       }
+      __syncthreads();
+      if (tid == 0) c_visit += (unsigned long long)L;
       // short segments: each wave takes a contiguous range of their visits;
       // every lane keeps U list loads in flight
       stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw) {
