@@ -23,12 +23,12 @@ struct Post {
 
 // Per-vector data used by the bounds of Section 3.2.2:
 //   cut  = |x'|, the number of unindexed leading components;
-//   xmw  = maxweight(x);
+//   len  = |x|, the number of components;
 //   pmw  = maxweight(x');
 //   pnrm = ||x'||_2 rounded up to float.
 struct RowStat {
   int32_t cut;
-  float xmw;
+  int32_t len;
   float pmw;
   float pnrm;
 };

@@ -147,7 +147,7 @@ __global__ void k_cutoff(const int64_t* __restrict__ rp, const RComp* __restrict
     for (int32_t k = 0; k < len; ++k) xm = fmaxf(xm, rc[a + k].w);
     RowStat s;
     s.cut = cut;
-    s.xmw = xm;
+    s.len = len;
     s.pmw = pm;
     // ||x'||_2 rounded up, with a relative nudge covering the double sqrt's rounding
     s.pnrm = sqp > 0.0 ? __double2float_ru(sqrt(sqp) * (1.0 + 0x1p-50)) : 0.0f;

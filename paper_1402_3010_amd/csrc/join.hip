@@ -106,7 +106,7 @@ struct Smem {
   };
   // survivor queue entries: the configured capacity less the tables' room
   static constexpr int SQE = C::SQ - (int)((sizeof(ShortTables) + 15) / 16);
-  uint4 sq[SQE];  // x = slot << 16 | y - dbase, y = fixed-point score (0 = dropped), z = row start, w = cut | len << 16
+  uint4 sq[SQE];  // x = slot << 16 | y - dbase, y = fixed-point score (0 = dropped), z unused, w = cut | len << 16
   ShortTables ss;
   RComp qrow[C::QB];     // staged components of the tile
   uint2 cur[C::QB];      // list cursor of each staged component: {position, vector id at it}
@@ -452,9 +452,10 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         const int qi = (int)(it.x >> 16);
         uint32_t cut = it.w & 0xFFFFu;
         if ((it.w >> 16) == 0xFFFFu) cut = (uint32_t)a.rs[dbase + (it.x & 0xFFFFu)].cut;
+        const uint32_t ys = (uint32_t)a.rp[dbase + (it.x & 0xFFFFu)];  // row offsets fit 32 bits (nnz < 2^32)
         float part = 0.0f;
         for (uint32_t k = (uint32_t)lane; k < cut; k += 64) {
-          const RComp c = a.rc[it.z + k];
+          const RComp c = a.rc[ys + k];
           part += qlookup(qi, c.r) * c.w;
         }
 #pragma unroll
@@ -471,11 +472,12 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       const int qi = (int)(it.x >> 16);
       uint32_t cut = it.w & 0xFFFFu;
       if ((it.w >> 16) == 0xFFFFu) cut = (uint32_t)a.rs[dbase + (it.x & 0xFFFFu)].cut;
+      const uint32_t ys = (uint32_t)a.rp[dbase + (it.x & 0xFFFFu)];
       float sc = (float)it.y * kInvFix;
       for (uint32_t k0 = 0; k0 < cut; k0 += 4) {
         RComp c[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = a.rc[it.z + (k0 + u < cut ? k0 + u : cut - 1)];
+        for (int u = 0; u < 4; ++u) c[u] = a.rc[ys + (k0 + u < cut ? k0 + u : cut - 1)];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           if (k0 + u < cut) sc += qlookup(qi, c[u].r) * c[u].w;
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         const uint4 it = sm.sq[base + l];
         const int qi = (int)(it.x >> 16);
         const int64_t y = dbase + (int64_t)(it.x & 0xFFFFu);
-        const int64_t ys = it.z;
+        const int64_t ys = a.rp[y];
         int ylen = (int)(it.w >> 16);
         if (ylen == 0xFFFF) ylen = (int)(a.rp[y + 1] - a.rp[y]);
         const RComp* yrow = a.rc + ys;
@@ -569,7 +571,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         const uint32_t kk = hkey[h];
         bool want = false, retry = false;
         int qi = 0, yl = 0;
-        uint32_t av = 0u, yst = 0u, packed = 0u;
+        uint32_t av = 0u, packed = 0u;
         if (kk) {
           qi = (int)((kk - 1u) >> 16);
           yl = (int)((kk - 1u) & 0xFFFFu);
@@ -577,9 +579,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           av = hval[h];
           if (y < a.n && !(a.triangle && y >= q0 + qi)) {
             const RowStat st = a.rs[y];
-            const uint32_t r0 = (uint32_t)a.rp[y];
-            const int ylen = (int)((uint32_t)a.rp[y + 1] - r0);
-            yst = r0;
+            const int ylen = st.len;
             packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
             const float A = (float)av;  // accumulator units, as the bounds
             const float4 qb = sm.qb[qi];
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           if (want) {
             const int slot = qb + (int)__popcll(wm & lt);
             if (slot < SQ) {
-              sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av, yst, packed);
+              sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av, 0u, packed);
               ++c_surv;
             } else {
               retry = true;
@@ -645,14 +645,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 
     // per-row data of the filter's first rows; the loads overlap the accumulation
     RowStat stN;
-    uint32_t ysN, ylN;
     auto load_rows = [&](int yi) {
       const int64_t y = blk0 + yi * NT + tid;
-      const int64_t yc = y < blk1 ? y : blk0;
-      stN = a.rs[yc];
-      const uint32_t r0 = (uint32_t)a.rp[yc];  // row offsets fit 32 bits (nnz < 2^32)
-      ysN = r0;
-      ylN = (uint32_t)a.rp[yc + 1] - r0;
+      stN = a.rs[y < blk1 ? y : blk0];
     };
     load_rows(0);
 
@@ -918,8 +913,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 #pragma unroll 1
       for (int yi = 0; yi < YPT; ++yi) {
         const RowStat st = stN;
-        const uint32_t yst = ysN;
-        const int ylen = (int)ylN;
+        const int ylen = st.len;
         if (yi + 1 < YPT) load_rows(yi + 1);
         const int yl = yi * NT + tid;
         const int64_t y = blk0 + yl;
@@ -965,7 +959,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
               if (want) {
                 const int slot = qb + (int)__popcll(wm & lt);
                 if (slot < SQ) {
-                  sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (yoff + (uint32_t)yl), av[qi], yst, packed);
+                  sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (yoff + (uint32_t)yl), av[qi], 0u, packed);
                   ++c_surv;
                 } else {
                   keep |= 1u << qi;
