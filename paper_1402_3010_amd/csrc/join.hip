@@ -731,33 +731,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) hn[j] = __builtin_amdgcn_raw_buffer_load_b32(hrs, (int)hq[j], 0, 0);
       }
-      // pass 2: sparse lists, usually one entry per block
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j) {
-        if (thit[j]) {
-          const int64_t k = cb + (int64_t)j * NT + tid;
-          uint32_t pos = tpos[j];
-          const uint32_t end = tend[j];
-          const int ab = tqi[j] * CB - (int)blk0;
-          atomicAdd(&sm.acc[ab + (int)t0[j].y], fixp(tw[j], t0[j].w));
-          ++c_tail;
-          ++pos;
-          uint32_t ny = pos < end ? t1y[j] : 0xFFFFFFFFu;
-          while ((int64_t)ny < blk1) {
-            const Post p = a.post[pos];
-            atomicAdd(&sm.acc[ab + (int)p.y], fixp(tw[j], p.w));
-            ++c_tail;
-            ++pos;
-            ny = pos < end ? a.post[pos].y : 0xFFFFFFFFu;
-          }
-          if (staged) {
-            sm.cur[k] = make_uint2(pos, ny);
-          } else {
-            gcur[2 * k] = pos;
-            gcur[2 * k + 1] = ny;
-          }
-        }
-      }
       // Allocation: an exclusive scan over the threads of (long segments,
       // short segments, short entries) places long segments at the front of
       // seg[] (one wave each) and short ones, in thread order, at the back
@@ -817,6 +790,35 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       }
       __syncthreads();
       if (tid == 0) c_visit += (unsigned long long)L;
+      // pass 2: sparse lists, usually one entry per block (after the
+      // allocation, whose barrier covers the first entries' loads; the
+      // accumulation commutes with the streams, so no barrier follows)
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        if (thit[j]) {
+          const int64_t k = cb + (int64_t)j * NT + tid;
+          uint32_t pos = tpos[j];
+          const uint32_t end = tend[j];
+          const int ab = tqi[j] * CB - (int)blk0;
+          atomicAdd(&sm.acc[ab + (int)t0[j].y], fixp(tw[j], t0[j].w));
+          ++c_tail;
+          ++pos;
+          uint32_t ny = pos < end ? t1y[j] : 0xFFFFFFFFu;
+          while ((int64_t)ny < blk1) {
+            const Post p = a.post[pos];
+            atomicAdd(&sm.acc[ab + (int)p.y], fixp(tw[j], p.w));
+            ++c_tail;
+            ++pos;
+            ny = pos < end ? a.post[pos].y : 0xFFFFFFFFu;
+          }
+          if (staged) {
+            sm.cur[k] = make_uint2(pos, ny);
+          } else {
+            gcur[2 * k] = pos;
+            gcur[2 * k + 1] = ny;
+          }
+        }
+      }
       // short segments: each wave takes a contiguous range of their visits;
       // every lane keeps U list loads in flight
       stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw) {
