@@ -262,9 +262,10 @@ int build_lists(apss_index* ix) {
   DBuf<int64_t> scan2;
   CHK(scan2.alloc(scan_tmp_elems(m + 1)), "alloc");
   CHK(exclusive_scan_i64(ix->off.p, m + 1, scan2.p, nullptr, s), "scan");
-  // one padding entry after the last list lets the join read position p + 1 for any p < P
-  CHK(ix->post.alloc(P + 1), "alloc");
-  CHK(fill_u64((uint64_t*)ix->post.p + P, ~0ull, 1, s), "fill");
+  // two padding entries after the last list let the join read positions p
+  // and p + 1 for any p <= P (p = 0 too when there are no lists)
+  CHK(ix->post.alloc(P + 2), "alloc");
+  CHK(fill_u64((uint64_t*)ix->post.p + P, ~0ull, 2, s), "fill");
   CHK(launch_unpack_post(ss.v64a.p, P, ix->post.p, s), "post");
   // the join's list loads put a chunk's base in the scalar offset, which the
   // hardware range check does not cover: 64 zero entries after the last list

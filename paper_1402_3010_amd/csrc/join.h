@@ -15,7 +15,7 @@ struct JoinArgs {
   const RComp* rc;        // [nnz] components, densest dimension first
   const RowStat* rs;      // [n]
   const int64_t* off;     // [m+1] list offsets by rank
-  const Post* post;       // [P]   list entries, vector ids ascending within a list
+  const Post* post;       // [P+2] list entries, vector ids ascending within a list; 2 padding entries
   const uint32_t* post4;  // [P+kPost4Pad] the same entries packed: id mod 2^16 | weight in 2^-15 units (rounded up) << 16
   uint32_t post4_bytes;   // size of post4 in bytes (< 2^32)
   const uint32_t* hoff;   // [(nb+1) * H] first entry of list r at or after block b

@@ -33,6 +33,8 @@
 #include "join.h"
 #include "rescore.h"
 
+#include <type_traits>
+
 namespace apss {
 
 namespace {
@@ -665,64 +667,74 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       uint32_t tpos[KMAX], tend[KMAX];
       float tw[KMAX];
       int tqi[KMAX];
+      // (one copy of the loop per tile kind; the staged one has no
+      // conditional loads, whose results later code would wait for)
+      auto pass1 = [&](auto kind) {
+        constexpr bool ST = decltype(kind)::value;
 #pragma unroll
-      for (int j = 0; j < KMAX; ++j) {
-        const int64_t k = cb + (int64_t)j * NT + tid;
-        bool has_seg = false;
-        Seg sg = {0u, 0u, 0u};
-        thit[j] = false;
-        hq[j] = 0xFFFFFFFFu;
-        tpos[j] = 0;
-        tend[j] = 0;
-        tw[j] = 0.0f;
-        tqi[j] = 0;
-        if (k < tile_nnz) {
-          RComp c;
-          int qi;
-          uint32_t pos, ny;
-          if (staged) {
-            c = sm.qrow[k];
-            qi = sm.cqi[k];
+        for (int j = 0; j < KMAX; ++j) {
+          const int64_t k = cb + (int64_t)j * NT + tid;
+          bool has_seg = false;
+          Seg sg = {0u, 0u, 0u};
+          thit[j] = false;
+          hq[j] = 0xFFFFFFFFu;
+          if constexpr (ST) {
+            // without branches around loads: k < QB, so the LDS reads stay
+            // in bounds, and a component that is not a sparse hit loads the
+            // lists' first entry instead of its own
+            const RComp c = sm.qrow[k];
+            const int qi = sm.cqi[k];
             const uint2 cu = sm.cur[k];
-            pos = cu.x;
-            ny = cu.y;
-          } else {
-            c = a.qrc[qbase + k];
-            qi = find_slot(qbase + k);
-            pos = gcur[2 * k];
-            ny = gcur[2 * k + 1];
-          }
-          if (pos == kDead) {
-            // no entry of this list in the item's range
-          } else if (c.r < a.H) {
-            uint32_t e;
-            if (staged) {
-              e = hn[j];
-              hq[j] = (uint32_t)c.r * 4u;  // prefetched below for the next block
-            } else {
-              e = hend[c.r];
-            }
-            if (e > pos) {
-              has_seg = true;
-              sg.pos = pos;
-              sg.lenq = (e - pos) | ((uint32_t)qi << 16);
-              sg.q = q15(c.w);
-              if (staged) sm.cur[k] = make_uint2(e, 0u);
-              else gcur[2 * k] = e;
-            }
-          } else if ((int64_t)ny < blk1) {
-            thit[j] = true;
+            const uint32_t pos = cu.x, ny = cu.y;
+            const bool live = k < tile_nnz && pos != kDead;
+            const bool dense = c.r < a.H;
+            const uint32_t e = hn[j];
+            if (live && dense) hq[j] = (uint32_t)c.r * 4u;  // prefetched below for the next block
+            has_seg = live && dense && e > pos;
+            sg.pos = pos;
+            sg.lenq = (e - pos) | ((uint32_t)qi << 16);
+            sg.q = q15(c.w);
+            if (has_seg) sm.cur[k] = make_uint2(e, 0u);
+            const bool hit = live && !dense && (int64_t)ny < blk1;
+            thit[j] = hit;
             tpos[j] = pos;
             tw[j] = c.w;
             tqi[j] = qi;
-            tend[j] = (uint32_t)a.off[c.r + 1];
-            t0[j] = a.post[pos];
-            t1y[j] = a.post[pos + 1].y;  // the list array carries one padding entry
+            const uint32_t pp = hit ? pos : 0u;
+            tend[j] = (uint32_t)a.off[hit ? c.r + 1 : 0];
+            t0[j] = a.post[pp];
+            t1y[j] = a.post[pp + 1].y;  // the list array carries one padding entry
+          } else if (k < tile_nnz) {
+            const RComp c = a.qrc[qbase + k];
+            const int qi = find_slot(qbase + k);
+            const uint32_t pos = gcur[2 * k], ny = gcur[2 * k + 1];
+            if (pos == kDead) {
+              // no entry of this list in the item's range
+            } else if (c.r < a.H) {
+              const uint32_t e = hend[c.r];
+              if (e > pos) {
+                has_seg = true;
+                sg.pos = pos;
+                sg.lenq = (e - pos) | ((uint32_t)qi << 16);
+                sg.q = q15(c.w);
+                gcur[2 * k] = e;
+              }
+            } else if ((int64_t)ny < blk1) {
+              thit[j] = true;
+              tpos[j] = pos;
+              tw[j] = c.w;
+              tqi[j] = qi;
+              tend[j] = (uint32_t)a.off[c.r + 1];
+              t0[j] = a.post[pos];
+              t1y[j] = a.post[pos + 1].y;
+            }
           }
+          sgj[j] = sg;
+          sk[j] = !has_seg ? 0 : ((sg.lenq & 0xFFFFu) >= (uint32_t)kLongSeg ? 2 : 1);
         }
-        sgj[j] = sg;
-        sk[j] = !has_seg ? 0 : ((sg.lenq & 0xFFFFu) >= (uint32_t)kLongSeg ? 2 : 1);
-      }
+      };
+      if (staged) pass1(std::integral_constant<bool, true>{});
+      else pass1(std::integral_constant<bool, false>{});
       // the dense lists' segment ends of the next block, for staged tiles:
       // unconditional buffer loads (a component with none reads out of
       // range, which returns 0), so nothing waits on them before that block
