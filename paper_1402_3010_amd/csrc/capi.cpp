@@ -914,21 +914,69 @@ int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_ro
     int rc = check_t(ix, t);
     if (rc) return rc;
   }
-  CsrDev in;
   int64_t nnz = 0;
-  int rc = stage_csr(s, nq, q_row_ptr, q_col, q_val, on_device, &nnz, in);
-  if (rc) return rc;
+  int rc;
   if ((rc = reset_err(ws))) return rc;
   uint32_t* err = ws.err.p;
   unsigned long long* bad = ws.bad.p;
-  CHK(launch_check_rowptr(in.prp, nq, nnz, err, bad, s), "check row_ptr");
-  if ((rc = check_err(s, err, bad, "query"))) return rc;
+  const int64_t* prp;
+  const int32_t* pcol;
+  const float* pval;
+  CsrDev in;
   rows.n = nq;
+  if (on_device) {
+    if ((rc = stage_csr(s, nq, q_row_ptr, q_col, q_val, on_device, &nnz, in))) return rc;
+    CHK(launch_check_rowptr(in.prp, nq, nnz, err, bad, s), "check row_ptr");
+    if ((rc = check_err(s, err, bad, "query"))) return rc;
+    CHK(rows.rp.reserve(nq + 1), "alloc");
+    CHK(hipMemcpyAsync(rows.rp.p, in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToDevice, s), "copy");
+    rows.rp_host.resize((size_t)nq + 1);
+    CHK(hipMemcpyAsync(rows.rp_host.data(), in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s), "copy");
+    prp = in.prp;
+    pcol = in.pcol;
+    pval = in.pval;
+  } else {
+    // host rows: checked here, copied into the workspace's kept buffers,
+    // with no synchronisation before the single error check below
+    nnz = q_row_ptr[nq];
+    if (q_row_ptr[0] != 0 || nnz < 0 || nnz >= (1ll << 32)) {
+      set_error("row_ptr must start at 0 and end at nnz in [0, 2^32)");
+      return APSS_EINVAL;
+    }
+    for (int64_t r = 0; r < nq; ++r)
+      if (q_row_ptr[r + 1] < q_row_ptr[r]) {
+        set_error("row_ptr must be non-decreasing (row %lld)", (long long)r);
+        return APSS_EINVAL;
+      }
+    // every buffer is reserved before the first copy of the caller's
+    // memory is queued, so no early return leaves such a copy in flight
+    CHK(rows.rp.reserve(nq + 1), "alloc");
+    CHK(ws.q_col.reserve(nnz), "alloc");
+    CHK(ws.q_val.reserve(nnz), "alloc");
+    CHK(rows.rc.reserve(nnz), "alloc");
+    CHK(rows.mw.reserve(nq), "alloc");
+    CHK(ws.ss.k1.reserve(nnz), "alloc");
+    CHK(ws.ss.v32a.reserve(nnz), "alloc");
+    CHK(ws.ss.k2.reserve(nnz), "sort scratch");
+    CHK(ws.ss.v32b.reserve(nnz), "sort scratch");
+    CHK(ws.ss.hist.reserve(radix_hist_elems(nnz)), "sort scratch");
+    CHK(ws.ss.scan.reserve(radix_scan_tmp_elems(nnz)), "sort scratch");
+    if (t_per_row) CHK(ws.qt.reserve(nq), "alloc");
+    CHK(hipMemcpyAsync(rows.rp.p, q_row_ptr, sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, s), "copy csr");
+    if (nnz) {
+      CHK(hipMemcpyAsync(ws.q_col.p, q_col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s), "copy csr");
+      CHK(hipMemcpyAsync(ws.q_val.p, q_val, sizeof(float) * nnz, hipMemcpyHostToDevice, s), "copy csr");
+    }
+    rows.rp_host.assign(q_row_ptr, q_row_ptr + nq + 1);
+    prp = rows.rp.p;
+    pcol = ws.q_col.p;
+    pval = ws.q_val.p;
+  }
   rows.nnz = nnz;
-  CHK(rows.rp.reserve(nq + 1), "alloc");
-  CHK(hipMemcpyAsync(rows.rp.p, in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToDevice, s), "copy");
-  rows.rp_host.resize((size_t)nq + 1);
-  CHK(hipMemcpyAsync(rows.rp_host.data(), in.prp, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost, s), "copy");
+  if (t_per_row) {
+    CHK(ws.qt.reserve(nq), "alloc");
+    CHK(hipMemcpyAsync(ws.qt.p, t_per_row, sizeof(float) * nq, hipMemcpyHostToDevice, s), "copy thresholds");
+  }
   CHK(rows.rc.reserve(nnz), "alloc");
   CHK(rows.mw.reserve(nq), "alloc");
   SortScratch& ss = ws.ss;
@@ -936,18 +984,12 @@ int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_ro
   CHK(ss.v32a.reserve(nnz), "alloc");
   const int rbits = ceil_log2((uint64_t)ix->m);
   const int nbits = ceil_log2((uint64_t)std::max<int64_t>(nq, 1));
-  CHK(launch_query_keys(in.prp, in.pcol, in.pval, ix->rank.p, nq, ix->m, rbits, 1e-5, ss.k1.p, ss.v32a.p, rows.mw.p,
-                        err, bad, s),
+  // invalid dimensions get a valid key, so the sort runs before the check
+  CHK(launch_query_keys(prp, pcol, pval, ix->rank.p, nq, ix->m, rbits, 1e-5, ss.k1.p, ss.v32a.p, rows.mw.p, err, bad, s),
       "query keys");
-  if ((rc = check_err(s, err, bad, "query"))) return rc;
   if ((rc = sort_rows(ws, ss.k1.p, ss.v32a.p, nnz, nbits + rbits, rbits, rows.rc.p, err))) return rc;
-  if ((rc = check_err(s, err, nullptr, "query"))) return rc;
-  if (t_per_row) {
-    CHK(ws.qt.reserve(nq), "alloc");
-    CHK(hipMemcpyAsync(ws.qt.p, t_per_row, sizeof(float) * nq, hipMemcpyHostToDevice, s), "copy thresholds");
-    // t_per_row is borrowed: finish the copy before returning
-    CHK(hipStreamSynchronize(s), "copy thresholds");
-  }
+  // also completes the copies of the caller's host buffers (borrowed)
+  if ((rc = check_err(s, err, bad, "query"))) return rc;
   return APSS_OK;
 }
 

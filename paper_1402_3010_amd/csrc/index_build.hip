@@ -219,16 +219,21 @@ __global__ void k_block_offsets(const int64_t* __restrict__ off, const Post* __r
 }
 
 // Query rows: dimension ids -> ranks (keys (row, rank)), with input checks.
+// One wave per row: lanes over its components (coalesced), then the row's
+// squared norm, maxweight and error flags reduced across the wave in a
+// fixed order.
 __global__ void k_query_keys(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, const float* __restrict__ val,
                              const int32_t* __restrict__ rank, int64_t nq, int64_t m, int rbits, double norm_tol,
                              uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, float* __restrict__ qmw,
                              uint32_t* __restrict__ err, unsigned long long* __restrict__ bad_row) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nq; r += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int64_t wpb = (int64_t)(blockDim.x >> 6);
+  for (int64_t r = (int64_t)blockIdx.x * wpb + (int64_t)(threadIdx.x >> 6); r < nq; r += (int64_t)gridDim.x * wpb) {
     const int64_t a = rp[r], b = rp[r + 1];
     uint32_t e = 0;
     double ss = 0.0;
     float mx = 0.0f;
-    for (int64_t k = a; k < b; ++k) {
+    for (int64_t k = a + lane; k < b; k += 64) {
       const int32_t d = col[k];
       const float w = val[k];
       if (d < 0 || (int64_t)d >= m) {
@@ -242,11 +247,19 @@ __global__ void k_query_keys(const int64_t* __restrict__ rp, const int32_t* __re
       mx = fmaxf(mx, w);
       vals[k] = __float_as_uint(w);
     }
-    if (b > a && !(fabs(sqrt(ss) - 1.0) <= norm_tol)) e |= ERR_NORM;
-    qmw[r] = mx;
-    if (e) {
-      atomicOr(err, e);
-      atomicMin(bad_row, (unsigned long long)r);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      ss += __shfl_xor(ss, o, 64);
+      mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+      e |= __shfl_xor(e, o, 64);
+    }
+    if (lane == 0) {
+      if (b > a && !(fabs(sqrt(ss) - 1.0) <= norm_tol)) e |= ERR_NORM;
+      qmw[r] = mx;
+      if (e) {
+        atomicOr(err, e);
+        atomicMin(bad_row, (unsigned long long)r);
+      }
     }
   }
 }
@@ -345,8 +358,11 @@ hipError_t launch_block_offsets(const int64_t* off, const Post* post, int32_t H,
 hipError_t launch_query_keys(const int64_t* rp, const int32_t* col, const float* val, const int32_t* rank, int64_t nq,
                              int64_t m, int rbits, double tol, uint64_t* keys, uint32_t* vals, float* qmw,
                              uint32_t* err, unsigned long long* bad, hipStream_t s) {
-  LAUNCH(k_query_keys, nq, rp, col, val, rank, nq, m, rbits, tol, keys, vals, qmw, err, bad);
-  return hipSuccess;
+  if (nq <= 0) return hipSuccess;
+  const int64_t blocks = (nq + 3) / 4;  // 4 waves of 64 lanes per block, one row per wave
+  hipLaunchKernelGGL(k_query_keys, dim3((unsigned)(blocks < 32768 ? blocks : 32768)), dim3(256), 0, s, rp, col, val, rank,
+                     nq, m, rbits, tol, keys, vals, qmw, err, bad);
+  return hipGetLastError();
 }
 
 }  // namespace apss

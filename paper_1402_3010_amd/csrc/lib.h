@@ -101,6 +101,9 @@ struct Workspace {
   DBuf<uint64_t> raw_key;
   DBuf<float> raw_sim;
   DBuf<float> qt;
+  // query CSR copied from the host (kept between calls)
+  DBuf<int32_t> q_col;
+  DBuf<float> q_val;
   DBuf<uint32_t> err;
   DBuf<unsigned long long> bad;
   // head screen of the screened join
@@ -119,7 +122,7 @@ struct Workspace {
   }
   int64_t bytes() const {
     return ss.bytes() + tstart.bytes() + qcum.bytes() + qctr.bytes() + wg_cur.bytes() + counters.bytes() +
-           raw_key.bytes() + raw_sim.bytes() + qt.bytes() + s_keys.bytes() + s_cand.bytes() + s_sid.bytes() +
+           raw_key.bytes() + raw_sim.bytes() + qt.bytes() + q_col.bytes() + q_val.bytes() + s_keys.bytes() + s_cand.bytes() + s_sid.bytes() +
            s_tiles.bytes() + s_nh.bytes() + s_X.bytes();
   }
 };

@@ -152,7 +152,36 @@ int validate_request(const apss_index* ix, int64_t nq, const int64_t* rp, const 
 }
 
 // Run one batch on a slot's workspace; fills every request's result.
-void run_batch(apss_server* S, Workspace& ws, RankRows& rows, std::vector<Request*>& batch) {
+// Page-locked host buffer that only grows (a batch's queries are packed
+// here, so their copies to the device run asynchronously by DMA).
+template <class T>
+struct PinnedBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  bool reserve(size_t k) {
+    if (k <= n) return true;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    if (hipHostMalloc((void**)&p, (k > 0 ? k : 1) * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    n = k;
+    return true;
+  }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+struct Staging {
+  PinnedBuf<int64_t> rp;
+  PinnedBuf<int32_t> col;
+  PinnedBuf<float> val, tq;
+};
+
+void run_batch(apss_server* S, Workspace& ws, RankRows& rows, Staging& hs, std::vector<Request*>& batch) {
   apss_index* ix = S->ix;
   int64_t nq = 0, nnz = 0, cap = 0;
   for (Request* r : batch) {
@@ -160,18 +189,27 @@ void run_batch(apss_server* S, Workspace& ws, RankRows& rows, std::vector<Reques
     nnz += r->nnz;
     cap += S->o.pairs_per_query * r->nq;
   }
-  std::vector<int64_t> rp((size_t)nq + 1);
-  std::vector<int32_t> col((size_t)nnz);
-  std::vector<float> val((size_t)nnz), tq((size_t)nq);
   std::vector<int64_t> row0(batch.size() + 1);
+  if (!hs.rp.reserve((size_t)nq + 1) || !hs.col.reserve((size_t)nnz) || !hs.val.reserve((size_t)nnz) ||
+      !hs.tq.reserve((size_t)nq)) {
+    for (Request* r : batch) {
+      r->status = APSS_ENOMEM;
+      r->error = "pinned host allocation failed";
+    }
+    return;
+  }
+  int64_t* const rp = hs.rp.p;
+  int32_t* const col = hs.col.p;
+  float* const val = hs.val.p;
+  float* const tq = hs.tq.p;
   int64_t q0 = 0, k0 = 0;
   for (size_t b = 0; b < batch.size(); ++b) {
     Request* r = batch[b];
     row0[b] = q0;
     for (int64_t q = 0; q < r->nq; ++q) rp[(size_t)(q0 + q)] = k0 + r->rp[(size_t)q];
-    std::copy(r->col.begin(), r->col.end(), col.begin() + k0);
-    std::copy(r->val.begin(), r->val.end(), val.begin() + k0);
-    std::copy(r->t.begin(), r->t.end(), tq.begin() + q0);
+    std::copy(r->col.begin(), r->col.end(), col + k0);
+    std::copy(r->val.begin(), r->val.end(), val + k0);
+    std::copy(r->t.begin(), r->t.end(), tq + q0);
     q0 += r->nq;
     k0 += r->nnz;
   }
@@ -181,7 +219,7 @@ void run_batch(apss_server* S, Workspace& ws, RankRows& rows, std::vector<Reques
   apss_pairs all{0, nullptr, nullptr, nullptr};
   int rc = APSS_OK;
   if (nq > 0) {
-    rc = stage_queries(ix, ws, nq, rp.data(), col.data(), val.data(), 0, tq.data(), 1.0f, rows);
+    rc = stage_queries(ix, ws, nq, rp, col, val, 0, tq, 1.0f, rows);
     int64_t cnt = 0;
     if (!rc) {
       const QuerySet Q{rows.rp.p, rows.rc.p, rows.mw.p, rows.n, rows.nnz, rows.rp_host.data()};
@@ -219,6 +257,7 @@ void run_batch(apss_server* S, Workspace& ws, RankRows& rows, std::vector<Reques
 }
 
 void worker(apss_server* S, int slot) {
+  Staging hs;  // destroyed last, after the slot's stream has drained
   Workspace ws;
   RankRows rows;
   int rc = APSS_OK;
@@ -272,7 +311,7 @@ void worker(apss_server* S, int slot) {
     }
     if (more) S->cv_work.notify_one();
     const int64_t regrows0 = ws.regrows;
-    run_batch(S, ws, rows, batch);
+    run_batch(S, ws, rows, hs, batch);
     {
       std::lock_guard<std::mutex> lk(S->mu);
       const Clock::time_point now = Clock::now();
