@@ -280,3 +280,47 @@ def test_every_tile_variant(apss, variant):
     assert_parity(i, j, s, oracle.join_plain(V, t), float(t), V)
     pre = oracle.join_prefix(V, t, 4)
     assert st["candidates"] == pre.candidates
+
+
+@pytest.mark.parametrize("range_rows", [1024, 4096, 131072])
+def test_range_widths(apss, range_rows):
+    # narrow ranges (many work items, hashed items), and one range wider than
+    # 65,536 rows, where survivors are drained after every block instead of
+    # sharing the queue across the item's blocks (no hashed items either)
+    V = make_corpus(spec_for("c2", n=9000))
+    t = np.float32(0.6)
+    i, j, s, st = gpu_join(apss, V, t, range_rows=range_rows)
+    assert_parity(i, j, s, oracle.join_plain(V, t), float(t), V)
+    pre = oracle.join_prefix(V, t, 4)
+    assert st["candidates"] == pre.candidates
+    assert st["matches"] == len(i)
+
+
+def test_query_device_input_matches_host(apss):
+    # the same queries given as device tensors take the device staging path
+    # (row offsets checked on the device); the pairs are bitwise the same
+    import torch
+    from types import SimpleNamespace
+    V = make_corpus(spec_for("c2", n=6000))
+    Q = V.take_rows(np.arange(3, 6000, 41))
+    tq = np.random.default_rng(7).uniform(0.5, 0.9, size=Q.n).astype(np.float32)
+    D = SimpleNamespace(n=Q.n, row_ptr=torch.from_numpy(Q.row_ptr).cuda(), col=torch.from_numpy(Q.col).cuda(),
+                        val=torch.from_numpy(Q.val).cuda())
+    ix = apss.Index.build(V, np.float32(0.5))
+    try:
+        hi, hj, hs = ix.query(Q, t_per_row=tq)
+        di, dj, ds = ix.query(D, t_per_row=tq)
+        # bad queries are refused by both paths and leave the index usable
+        bad = Csr(2, V.m, np.array([0, 1, 2]), np.array([3, V.m + 5], np.int32), np.array([1.0, 1.0], np.float32))
+        for B in (bad, SimpleNamespace(n=2, row_ptr=torch.from_numpy(bad.row_ptr).cuda(),
+                                       col=torch.from_numpy(bad.col).cuda(), val=torch.from_numpy(bad.val).cuda())):
+            with pytest.raises(apss.ApssError) as e:
+                ix.query(B, t=0.6)
+            assert e.value.code == apss.APSS_EINVAL
+        ai, aj, as_ = ix.query(Q, t_per_row=tq)
+    finally:
+        ix.close()
+    assert np.array_equal(hi, di) and np.array_equal(hj, dj) and np.array_equal(hs, ds)
+    assert np.array_equal(hi, ai) and np.array_equal(hj, aj) and np.array_equal(hs, as_)
+    ref = oracle.query(V, Q, t_per_row=tq.astype(np.float64))
+    assert_parity(hi, hj, hs, ref, None, Q, V, per_row_t=tq.astype(np.float64))
