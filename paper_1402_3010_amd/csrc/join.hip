@@ -769,14 +769,17 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         }
         if (lane == 63) sm.wsum2[wave] = make_uint2(icnt, ilen);
         __syncthreads();
-        uint32_t wc = 0u, wl = 0u, tc = 0u, tl = 0u;  // earlier waves, all waves
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
+        // totals of the earlier waves, then of all waves (uniform loops:
+        // no per-wave predicates to keep in registers)
+        uint32_t wc = 0u, wl = 0u;
+        for (int w = 0; w < wave; ++w) {
           const uint2 v = sm.wsum2[w];
-          if (w < wave) {
-            wc += v.x;
-            wl += v.y;
-          }
+          wc += v.x;
+          wl += v.y;
+        }
+        uint32_t tc = wc, tl = wl;
+        for (int w = wave; w < NW; ++w) {
+          const uint2 v = sm.wsum2[w];
           tc += v.x;
           tl += v.y;
         }
