@@ -23,12 +23,15 @@
 //     A + ||q_u|| ||y'|| >= t (Cauchy-Schwarz; q_u is q restricted to the
 //     dimensions that can be unindexed, so ||q_u|| <= 1, and it is q's head
 //     part when every row's unindexed part is its head); all with a small slack.
-//  3. verify survivors: s = A + dot(q, y') (one lane per survivor).
+//  3. verify survivors: s = A + dot(q, y') (one wave per survivor when few,
+//     else one lane per survivor); survivors of an item's blocks share one
+//     queue and are verified together.
 //  4. rescore verified pairs over the full rows in float with compensated
 //     products and sums (Ogita, Rump and Oishi 2005, Dot2) in a fixed
 //     lane-strided order and a fixed butterfly, so the result depends only on
 //     (q, y); if it lies within kBand of t the pair is decided by a double
-//     rescore.  Emitted pairs are compacted per wave (ballot + prefix).
+//     rescore.  One wave per pair; each kept pair takes its output slot from
+//     a global atomic counter.
 #include "apss_internal.h"
 #include "join.h"
 #include "rescore.h"
