@@ -65,7 +65,7 @@ typedef struct {
                             library's default.  The environment variable APSS_VARIANT overrides it. */
   int32_t head_dims;     /* densest dimensions that get per-block list offsets (0 = default) */
   int32_t range_rows;    /* corpus rows per work item of the join (rounded down to a multiple of the
-                            variant's block rows; 0 = default 8192).  The environment variable
+                            variant's block rows; 0 = default 16384).  The environment variable
                             APSS_RANGE_ROWS overrides it. */
   int32_t screen_dims;   /* > 0 (at most 8192): apss_join / apss_join_device use the screened join
                             with this many densest dimensions as the dense head (bf16 MFMA screen
