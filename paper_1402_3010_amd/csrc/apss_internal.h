@@ -77,8 +77,10 @@ void set_error(const char* fmt, ...);
 int64_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan_i64(int64_t* data, int64_t n, int64_t* tmp, int64_t* total_dev, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) pairs by bits [0, key_bits) of the key.
-// Sorted result ends in keys/vals; ktmp/vtmp are equal-sized scratch.
+// Stable sort of (key, value) pairs by key; keys must be below 2^key_bits.
+// LSD radix passes over 8-bit digits, or for up to 8,192 pairs with at most
+// 51 key bits one workgroup in LDS.  Sorted result ends in keys/vals;
+// ktmp/vtmp are equal-sized scratch.
 // hist must hold radix_hist_elems(n) int64.
 int64_t radix_hist_elems(int64_t n);
 int64_t radix_scan_tmp_elems(int64_t n);

@@ -200,10 +200,59 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
   }
 }
 
+// Small inputs (n <= kSmallSort): one workgroup sorts in LDS with a bitonic
+// network over (key << 13 | original index), so equal keys keep their input
+// order (stable, like the radix passes) in one launch instead of four passes
+// of three kernels each.  Keys are below 2^key_bits (every caller's keys are).
+constexpr int kSmallSort = 8192;
+constexpr int kSmallBits = 13;  // index bits
+
+template <typename V>
+__global__ __launch_bounds__(1024) void k_small_sort(uint64_t* __restrict__ keys, V* __restrict__ vals, int n) {
+  __shared__ uint64_t ck[kSmallSort];
+  __shared__ V ov[kSmallSort];
+  const int tid = (int)threadIdx.x;
+  int n2 = 2;
+  while (n2 < n) n2 <<= 1;
+  for (int i = tid; i < n2; i += (int)blockDim.x) {
+    if (i < n) {
+      ck[i] = (keys[i] << kSmallBits) | (uint64_t)i;
+      ov[i] = vals[i];
+    } else {
+      ck[i] = ~0ull;  // above every real entry
+    }
+  }
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < n2 / 2; i += (int)blockDim.x) {
+        const int lo = 2 * i - (i & (stride - 1));  // lower index of pair i, bit 'stride' clear
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t x = ck[lo], y = ck[hi];
+        if ((x > y) == up) {
+          ck[lo] = y;
+          ck[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int p = tid; p < n; p += (int)blockDim.x) {
+    const uint64_t c = ck[p];
+    keys[p] = c >> kSmallBits;
+    vals[p] = ov[c & ((1u << kSmallBits) - 1u)];
+  }
+}
+
 template <typename V>
 hipError_t radix_sort_impl(uint64_t* keys, V* vals, uint64_t* ktmp, V* vtmp, int64_t n, int key_bits, int64_t* hist,
                            int64_t* scan_tmp, hipStream_t s) {
   if (n <= 1 || key_bits <= 0) return hipSuccess;
+  if (n <= kSmallSort && key_bits <= 64 - kSmallBits) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_sort<V>), dim3(1), dim3(1024), 0, s, keys, vals, (int)n);
+    return hipGetLastError();
+  }
   const int64_t nblk = (n + kRsTile - 1) / kRsTile;
   uint64_t *ka = keys, *kb = ktmp;
   V *va = vals, *vb = vtmp;
