@@ -88,6 +88,10 @@ hipError_t radix_sort_u64(uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64
                           int key_bits, int64_t* hist, int64_t* scan_tmp, hipStream_t s);
 hipError_t radix_sort_u64_u32(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n,
                               int key_bits, int64_t* hist, int64_t* scan_tmp, hipStream_t s);
+// Independent stable sorts of the segments [seg[b], seg[b + 1]), b < nseg,
+// each of at most kSortSegment pairs (keys below 2^51), one workgroup each.
+constexpr int64_t kSortSegment = 8192;
+hipError_t segment_sort_u64_u32(uint64_t* keys, uint32_t* vals, const int64_t* seg, int64_t nseg, hipStream_t s);
 
 // Fill helpers (graph-safe kernels rather than memset nodes).
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

@@ -66,10 +66,35 @@ using namespace apss;
 namespace {
 
 // Sort (row, rank) keys with float payload into rank-space rows; checks for duplicates.
+// Rows are contiguous in row-major order, so with the row index in the key's
+// high bits sorting groups of whole rows independently sorts the whole
+// array: given the host row offsets, rows are grouped into segments of at
+// most kSortSegment entries, one workgroup each (one launch); otherwise, or
+// when a row is longer, radix passes over the whole array.
 int sort_rows(Workspace& ws, uint64_t* keys, uint32_t* vals, int64_t nnz, int key_bits, int rbits, RComp* rc_out,
-              uint32_t* err_dev) {
+              uint32_t* err_dev, const int64_t* rp_host = nullptr, int64_t nrows = 0) {
   hipStream_t s = ws.stream;
   SortScratch& ss = ws.ss;
+  if (rp_host && nnz > kSortSegment && key_bits <= 51) {
+    std::vector<int64_t>& seg = ss.seg_host;
+    seg.clear();
+    seg.push_back(0);
+    bool fits = true;
+    for (int64_t r = 0; r < nrows && fits; ++r) {
+      const int64_t e = rp_host[r + 1];
+      if (e - rp_host[r] > kSortSegment) fits = false;
+      else if (e - seg.back() > kSortSegment) seg.push_back(rp_host[r]);
+    }
+    if (fits) {
+      if (seg.back() != nnz) seg.push_back(nnz);
+      const int64_t nseg = (int64_t)seg.size() - 1;
+      CHK(ss.seg.reserve(nseg + 1), "sort scratch");
+      CHK(hipMemcpyAsync(ss.seg.p, seg.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s), "row sort");
+      CHK(segment_sort_u64_u32(keys, vals, ss.seg.p, nseg, s), "row sort");
+      CHK(launch_unpack_rows(keys, vals, nnz, rbits, rc_out, err_dev, s), "row unpack");
+      return APSS_OK;
+    }
+  }
   CHK(ss.k2.reserve(nnz), "sort scratch");
   CHK(ss.v32b.reserve(nnz), "sort scratch");
   CHK(ss.hist.reserve(radix_hist_elems(nnz)), "sort scratch");
@@ -963,6 +988,7 @@ int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_ro
     CHK(ws.ss.v32b.reserve(nnz), "sort scratch");
     CHK(ws.ss.hist.reserve(radix_hist_elems(nnz)), "sort scratch");
     CHK(ws.ss.scan.reserve(radix_scan_tmp_elems(nnz)), "sort scratch");
+    CHK(ws.ss.seg.reserve(nq + 2), "sort scratch");
     if (t_per_row) CHK(ws.qt.reserve(nq), "alloc");
     CHK(hipMemcpyAsync(rows.rp.p, q_row_ptr, sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, s), "copy csr");
     if (nnz) {
@@ -989,7 +1015,8 @@ int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_ro
   // invalid dimensions get a valid key, so the sort runs before the check
   CHK(launch_query_keys(prp, pcol, pval, ix->rank.p, nq, ix->m, rbits, 1e-5, ss.k1.p, ss.v32a.p, rows.mw.p, err, bad, s),
       "query keys");
-  if ((rc = sort_rows(ws, ss.k1.p, ss.v32a.p, nnz, nbits + rbits, rbits, rows.rc.p, err))) return rc;
+  if ((rc = sort_rows(ws, ss.k1.p, ss.v32a.p, nnz, nbits + rbits, rbits, rows.rc.p, err, rows.rp_host.data(), nq)))
+    return rc;
   // also completes the copies of the caller's host buffers (borrowed)
   if ((rc = check_err(s, err, bad, "query"))) return rc;
   return APSS_OK;

@@ -60,9 +60,11 @@ struct SortScratch {
   DBuf<uint64_t> k1, k2, v64a, v64b;
   DBuf<uint32_t> v32a, v32b;
   DBuf<int64_t> hist, scan;
+  DBuf<int64_t> seg;             // segment bounds of a segmented row sort
+  std::vector<int64_t> seg_host;  // their host copy (kept until the copy is done)
   int64_t bytes() const {
     return k1.bytes() + k2.bytes() + v64a.bytes() + v64b.bytes() + v32a.bytes() + v32b.bytes() + hist.bytes() +
-           scan.bytes();
+           scan.bytes() + seg.bytes();
   }
 };
 

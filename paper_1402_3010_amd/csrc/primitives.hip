@@ -204,14 +204,24 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
 // network over (key << 13 | original index), so equal keys keep their input
 // order (stable, like the radix passes) in one launch instead of four passes
 // of three kernels each.  Keys are below 2^key_bits (every caller's keys are).
-constexpr int kSmallSort = 8192;
+constexpr int kSmallSort = (int)kSortSegment;
 constexpr int kSmallBits = 13;  // index bits
 
+// seg == nullptr: one block sorts keys[0, n); else block b sorts the
+// segment [seg[b], seg[b + 1]) (at most kSmallSort entries).
 template <typename V>
-__global__ __launch_bounds__(1024) void k_small_sort(uint64_t* __restrict__ keys, V* __restrict__ vals, int n) {
+__global__ __launch_bounds__(1024) void k_small_sort(uint64_t* __restrict__ keys, V* __restrict__ vals, int n,
+                                                     const int64_t* __restrict__ seg) {
   __shared__ uint64_t ck[kSmallSort];
   __shared__ V ov[kSmallSort];
   const int tid = (int)threadIdx.x;
+  if (seg) {
+    const int64_t b0 = seg[blockIdx.x];
+    n = (int)(seg[blockIdx.x + 1] - b0);
+    keys += b0;
+    vals += b0;
+  }
+  if (n <= 1) return;
   int n2 = 2;
   while (n2 < n) n2 <<= 1;
   for (int i = tid; i < n2; i += (int)blockDim.x) {
@@ -250,7 +260,8 @@ hipError_t radix_sort_impl(uint64_t* keys, V* vals, uint64_t* ktmp, V* vtmp, int
                            int64_t* scan_tmp, hipStream_t s) {
   if (n <= 1 || key_bits <= 0) return hipSuccess;
   if (n <= kSmallSort && key_bits <= 64 - kSmallBits) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_sort<V>), dim3(1), dim3(1024), 0, s, keys, vals, (int)n);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_sort<V>), dim3(1), dim3(1024), 0, s, keys, vals, (int)n,
+                       (const int64_t*)nullptr);
     return hipGetLastError();
   }
   const int64_t nblk = (n + kRsTile - 1) / kRsTile;
@@ -310,6 +321,14 @@ hipError_t radix_sort_u64(uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64
 hipError_t radix_sort_u64_u32(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n, int key_bits,
                               int64_t* hist, int64_t* scan_tmp, hipStream_t s) {
   return radix_sort_impl<uint32_t>(keys, vals, ktmp, vtmp, n, key_bits, hist, scan_tmp, s);
+}
+
+hipError_t segment_sort_u64_u32(uint64_t* keys, uint32_t* vals, const int64_t* seg, int64_t nseg, hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  if (nseg > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_sort<uint32_t>), dim3((unsigned)nseg), dim3(1024), 0, s, keys, vals, 0,
+                     seg);
+  return hipGetLastError();
 }
 
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
