@@ -547,7 +547,9 @@ int ensure_pair_capacity(Workspace& ws, int64_t cap) {
 
 int sort_pairs(Workspace& ws, int64_t matches, int key_bits) {
   SortScratch& ss = ws.ss;
-  CHK(ss.k2.reserve(matches), "alloc sort");
+  // 1.5x: after the sort this scratch holds the unpacked (i, j, sim) arrays
+  // of finish_host, so that call never reallocates it under queued work
+  CHK(ss.k2.reserve(matches + matches / 2 + 1), "alloc sort");
   CHK(ss.v32b.reserve(matches), "alloc sort");
   CHK(ss.hist.reserve(radix_hist_elems(matches)), "alloc sort");
   CHK(ss.scan.reserve(radix_scan_tmp_elems(matches)), "alloc sort");
@@ -870,8 +872,17 @@ int check_t(const apss_index* ix, float t) {
   return APSS_OK;
 }
 
+// wait = false leaves the stream running; the caller synchronises and then
+// calls record_total.
+int record_total(Workspace& ws) {
+  float ms = 0.0f;
+  CHK(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[3]), "event");
+  ws.last.ms_total = ms;
+  return APSS_OK;
+}
+
 int finish_device(Workspace& ws, int64_t cnt, int bj, uint32_t* out_i, uint32_t* out_j, float* out_sim,
-                  int64_t capacity, int64_t* count) {
+                  int64_t capacity, int64_t* count, bool wait) {
   *count = cnt;
   if (cnt > capacity) {
     set_error("output capacity %lld too small for %lld pairs", (long long)capacity, (long long)cnt);
@@ -879,28 +890,28 @@ int finish_device(Workspace& ws, int64_t cnt, int bj, uint32_t* out_i, uint32_t*
   }
   CHK(launch_unpack_pairs(ws.raw_key.p, ws.raw_sim.p, cnt, bj, out_i, out_j, out_sim, ws.stream), "unpack");
   CHK(hipEventRecord(ws.ev[3], ws.stream), "event");
+  if (!wait) return APSS_OK;
   CHK(hipStreamSynchronize(ws.stream), "unpack");
-  float ms = 0.0f;
-  CHK(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[3]), "event");
-  ws.last.ms_total = ms;
-  return APSS_OK;
+  return record_total(ws);
 }
 
 int finish_host(Workspace& ws, int64_t cnt, int bj, apss_pairs* out) {
   out->count = 0;
   out->i = out->j = nullptr;
   out->sim = nullptr;
-  // the sort's second key buffer is free once the pairs are sorted: unpack there
+  // the sort's second key buffer is free once the pairs are sorted: unpack
+  // there, i, j and sim one after another, so that one copy brings them over
   SortScratch& ss = ws.ss;
-  CHK(ss.k2.reserve(cnt), "alloc");
-  CHK(ss.v32b.reserve(cnt), "alloc");
-  CHK(ss.v32a.reserve(cnt), "alloc");
+  CHK(ss.k2.reserve(cnt + cnt / 2 + 1), "alloc");
   uint32_t* di = (uint32_t*)ss.k2.p;
-  uint32_t* dj = ss.v32a.p;
-  float* ds = (float*)ss.v32b.p;
+  uint32_t* dj = di + cnt;
+  float* ds = (float*)(dj + cnt);
   int64_t c2 = 0;
-  int rc = finish_device(ws, cnt, bj, di, dj, ds, cnt, &c2);
-  if (rc) return rc;
+  int rc = finish_device(ws, cnt, bj, di, dj, ds, cnt, &c2, false);
+  if (rc) {
+    (void)hipStreamSynchronize(ws.stream);
+    return rc;
+  }
   const size_t nb = (size_t)(cnt > 0 ? cnt : 1);
   out->i = (uint32_t*)malloc(nb * sizeof(uint32_t));
   out->j = (uint32_t*)malloc(nb * sizeof(uint32_t));
@@ -911,15 +922,27 @@ int finish_host(Workspace& ws, int64_t cnt, int bj, apss_pairs* out) {
     free(out->sim);
     out->i = out->j = nullptr;
     out->sim = nullptr;
+    (void)hipStreamSynchronize(ws.stream);
     set_error("host allocation failed");
     return APSS_ENOMEM;
   }
-  if (cnt) {
-    CHK(hipMemcpyAsync(out->i, di, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
-    CHK(hipMemcpyAsync(out->j, dj, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
-    CHK(hipMemcpyAsync(out->sim, ds, sizeof(float) * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
+  // up to 4M pairs through the workspace's pinned staging in one copy;
+  // larger results straight into the output arrays
+  if (cnt && cnt <= (4ll << 20) && ws.host_out.reserve((size_t)(3 * cnt))) {
+    CHK(hipMemcpyAsync(ws.host_out.p, di, sizeof(uint32_t) * 3 * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
+    CHK(hipStreamSynchronize(ws.stream), "copy out");
+    memcpy(out->i, ws.host_out.p, sizeof(uint32_t) * cnt);
+    memcpy(out->j, ws.host_out.p + cnt, sizeof(uint32_t) * cnt);
+    memcpy(out->sim, ws.host_out.p + 2 * cnt, sizeof(float) * cnt);
+  } else {
+    if (cnt) {
+      CHK(hipMemcpyAsync(out->i, di, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
+      CHK(hipMemcpyAsync(out->j, dj, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
+      CHK(hipMemcpyAsync(out->sim, ds, sizeof(float) * cnt, hipMemcpyDeviceToHost, ws.stream), "copy out");
+    }
+    CHK(hipStreamSynchronize(ws.stream), "copy out");
   }
-  CHK(hipStreamSynchronize(ws.stream), "copy out");
+  if ((rc = record_total(ws))) return rc;
   out->count = cnt;
   return APSS_OK;
 }

@@ -56,6 +56,29 @@ struct RankRows {
 };
 
 // Sort scratch sized for the largest sort done so far.
+// Page-locked host buffer that only grows (copies from and to it run
+// asynchronously by DMA).
+template <class T>
+struct PinnedBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  bool reserve(size_t k) {
+    if (k <= n) return true;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    if (hipHostMalloc((void**)&p, (k > 0 ? k : 1) * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    n = k;
+    return true;
+  }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 struct SortScratch {
   DBuf<uint64_t> k1, k2, v64a, v64b;
   DBuf<uint32_t> v32a, v32b;
@@ -115,6 +138,7 @@ struct Workspace {
   DBuf<float> s_nh;
   DBuf<uint16_t> s_X;
   JoinGraph graph;
+  PinnedBuf<uint32_t> host_out;  // staging of result pairs copied to the host
   apss_stats last;
   int64_t regrows = 0;  // joins rerun because the pair buffer was too small
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -193,8 +217,11 @@ inline bool screen_variant_ok(int variant) { return variant_available(variant); 
 // Screened self-join of an index built with screen_dims > 0 (ix->screen set).
 int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, int64_t* count);
 // Unpack the sorted raw pairs into device arrays / library-owned host arrays.
+// finish_device waits for the unpack unless wait is false (then the caller
+// synchronises the stream and calls record_total).
 int finish_device(Workspace& ws, int64_t cnt, int bj, uint32_t* out_i, uint32_t* out_j, float* out_sim,
-                  int64_t capacity, int64_t* count);
+                  int64_t capacity, int64_t* count, bool wait = true);
+int record_total(Workspace& ws);
 int finish_host(Workspace& ws, int64_t cnt, int bj, apss_pairs* out);
 
 }  // namespace apss

@@ -152,29 +152,6 @@ int validate_request(const apss_index* ix, int64_t nq, const int64_t* rp, const 
 }
 
 // Run one batch on a slot's workspace; fills every request's result.
-// Page-locked host buffer that only grows (a batch's queries are packed
-// here, so their copies to the device run asynchronously by DMA).
-template <class T>
-struct PinnedBuf {
-  T* p = nullptr;
-  size_t n = 0;
-  bool reserve(size_t k) {
-    if (k <= n) return true;
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    n = 0;
-    if (hipHostMalloc((void**)&p, (k > 0 ? k : 1) * sizeof(T), hipHostMallocDefault) != hipSuccess) {
-      p = nullptr;
-      return false;
-    }
-    n = k;
-    return true;
-  }
-  ~PinnedBuf() {
-    if (p) (void)hipHostFree(p);
-  }
-};
-
 struct Staging {
   PinnedBuf<int64_t> rp;
   PinnedBuf<int32_t> col;
