@@ -570,50 +570,117 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     // in the table for the next pass
     dbase = rbeg;
     for (;;) {
+      if constexpr (QT >= 16) {
+        // 16-query tiles: G slots per thread at a time, their row-statistics
+        // loads issued together (unconditionally, row 0 for empty slots)
+        // before any is used.  (8-query tiles keep one slot at a time: the
+        // grouped form costs registers their block path needs.)
+        constexpr int G = (HS / NT) < 4 ? (HS / NT) : 4;
+        static_assert(G >= 1 && (HS / NT) % G == 0, "hash filter groups");
 #pragma unroll 1
-      for (int h0 = 0; h0 < HS; h0 += NT) {
-        const int h = h0 + tid;
-        const uint32_t kk = hkey[h];
-        bool want = false, retry = false;
-        int qi = 0, yl = 0;
-        uint32_t av = 0u, packed = 0u;
-        if (kk) {
-          qi = (int)((kk - 1u) >> 16);
-          yl = (int)((kk - 1u) & 0xFFFFu);
-          const int64_t y = rbeg + yl;
-          av = hval[h];
-          if (y < a.n && !(a.triangle && y >= q0 + qi)) {
-            const RowStat st = a.rs[y];
-            const int ylen = st.len;
-            packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
-            const float A = (float)av;  // accumulator units, as the bounds
-            const float4 qb = sm.qb[qi];
-            const float thr = qb.x, qm = qb.y;
-            want = ((float)ylen * qm >= thr) && (A + min_nonneg((float)st.cut * qm, qb.z) * st.pmw >= thr) &&
-                   (A + qb.w * st.pnrm >= thr);
-            ++c_cand;
+        for (int h0 = 0; h0 < HS; h0 += G * NT) {
+          uint32_t kk[G], hv[G];
+          int64_t yv[G];
+          bool ok[G];
+          RowStat stg[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int h = h0 + g * NT + tid;
+            kk[g] = hkey[h];
+            hv[g] = hval[h];
+            const int qi = (int)((kk[g] - 1u) >> 16);
+            yv[g] = rbeg + (int64_t)((kk[g] - 1u) & 0xFFFFu);
+            ok[g] = kk[g] != 0u && yv[g] < a.n && !(a.triangle && yv[g] >= q0 + qi);
+            stg[g] = a.rs[ok[g] ? yv[g] : 0];
           }
-        }
-        const uint64_t wm = __ballot(want);
-        if (wm) {
-          int qb = 0;
-          if (lane == 0) qb = atomicAdd(&sm.qcount, (int)__popcll(wm));
-          qb = __shfl(qb, 0);
-          if (want) {
-            const int slot = qb + (int)__popcll(wm & lt);
-            if (slot < SQ) {
-              sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av, 0u, packed);
-              ++c_surv;
-            } else {
-              retry = true;
-              --c_cand;
-              sm.ovf = 1;
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int h = h0 + g * NT + tid;
+            bool want = false, retry = false;
+            const int qi = (int)((kk[g] - 1u) >> 16);
+            const int yl = (int)((kk[g] - 1u) & 0xFFFFu);
+            const uint32_t av = hv[g];
+            uint32_t packed = 0u;
+            if (ok[g]) {
+              const RowStat st = stg[g];
+              const int ylen = st.len;
+              packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
+              const float A = (float)av;  // accumulator units, as the bounds
+              const float4 qb = sm.qb[qi];
+              const float thr = qb.x, qm = qb.y;
+              want = ((float)ylen * qm >= thr) && (A + min_nonneg((float)st.cut * qm, qb.z) * st.pmw >= thr) &&
+                     (A + qb.w * st.pnrm >= thr);
+              ++c_cand;
+            }
+            const uint64_t wm = __ballot(want);
+            if (wm) {
+              int qb = 0;
+              if (lane == 0) qb = atomicAdd(&sm.qcount, (int)__popcll(wm));
+              qb = __shfl(qb, 0);
+              if (want) {
+                const int slot = qb + (int)__popcll(wm & lt);
+                if (slot < SQ) {
+                  sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av, 0u, packed);
+                  ++c_surv;
+                } else {
+                  retry = true;
+                  --c_cand;
+                  sm.ovf = 1;
+                }
+              }
+            }
+            if (kk[g] && !retry) {
+              hkey[h] = 0u;
+              hval[h] = 0u;
             }
           }
         }
-        if (kk && !retry) {
-          hkey[h] = 0u;
-          hval[h] = 0u;
+      } else {
+#pragma unroll 1
+        for (int h0 = 0; h0 < HS; h0 += NT) {
+          const int h = h0 + tid;
+          const uint32_t kk = hkey[h];
+          bool want = false, retry = false;
+          int qi = 0, yl = 0;
+          uint32_t av = 0u, packed = 0u;
+          if (kk) {
+            qi = (int)((kk - 1u) >> 16);
+            yl = (int)((kk - 1u) & 0xFFFFu);
+            const int64_t y = rbeg + yl;
+            av = hval[h];
+            if (y < a.n && !(a.triangle && y >= q0 + qi)) {
+              const RowStat st = a.rs[y];
+              const int ylen = st.len;
+              packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
+              const float A = (float)av;  // accumulator units, as the bounds
+              const float4 qb = sm.qb[qi];
+              const float thr = qb.x, qm = qb.y;
+              want = ((float)ylen * qm >= thr) && (A + min_nonneg((float)st.cut * qm, qb.z) * st.pmw >= thr) &&
+                     (A + qb.w * st.pnrm >= thr);
+              ++c_cand;
+            }
+          }
+          const uint64_t wm = __ballot(want);
+          if (wm) {
+            int qb = 0;
+            if (lane == 0) qb = atomicAdd(&sm.qcount, (int)__popcll(wm));
+            qb = __shfl(qb, 0);
+            if (want) {
+              const int slot = qb + (int)__popcll(wm & lt);
+              if (slot < SQ) {
+                sm.sq[slot] = make_uint4(((uint32_t)qi << 16) | (uint32_t)yl, av, 0u, packed);
+                ++c_surv;
+              } else {
+                retry = true;
+                --c_cand;
+                sm.ovf = 1;
+              }
+            }
+          }
+          if (kk && !retry) {
+            hkey[h] = 0u;
+            hval[h] = 0u;
+          }
         }
       }
       __syncthreads();
