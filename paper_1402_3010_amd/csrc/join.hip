@@ -56,6 +56,14 @@ __device__ __forceinline__ uint32_t q15(float w) {
 }
 __device__ __forceinline__ uint32_t packed_product(uint32_t q, uint32_t e) { return __umul24(q, e >> 16); }
 
+// (p & mask) | base in one instruction (the compiler turns the OR of
+// disjoint bits back into an add and spends three instructions on it)
+__device__ __forceinline__ uint32_t and_or(uint32_t p, uint32_t mask, uint32_t base) {
+  uint32_t d;
+  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(d) : "v"(p), "s"(mask), "v"(base));
+  return d;
+}
+
 // Buffer descriptor of a device array (gfx9 resource word 3); loads through it
 // take a scalar base offset and are bounds-checked by the hardware.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
@@ -970,7 +978,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 #pragma unroll
           for (int u = 0; u < UL; ++u) {
             const uint32_t w = lane < ccnt[u] ? packed_product(cq[u], p[u]) : 0u;
-            atomicAdd(&sm.acc[cab[u] + (p[u] & (uint32_t)(CB - 1))], w);
+            atomicAdd(&sm.acc[and_or(p[u], (uint32_t)(CB - 1), cab[u])], w);
           }
         };
         uint32_t aoff[UL], aq[UL], pa[UL], boff[UL], bq[UL], pb[UL], aab[UL], bab[UL];
