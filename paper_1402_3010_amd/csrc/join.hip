@@ -108,22 +108,9 @@ struct Cfg {
 
 template <class C>
 struct Smem {
-  uint32_t acc[C::QT * C::CB];
-  float qd[C::QT * C::RD];
-  Seg seg[C::QB];
-  int32_t segpre[C::QB + 1];
-  // the short stream's tables
-  struct ShortTables {
-    uint8_t flag[C::NT / 64][C::U][64];  // segment-start flags: one row per wave and chunk of a batch
-    uint16_t first[C::QB * (kLongSeg - 1) / 64 + 2];  // segment holding each 64-entry chunk's first entry
-  };
-  // survivor queue entries: the configured capacity less the tables' room
-  static constexpr int SQE = C::SQ - (int)((sizeof(ShortTables) + 15) / 16);
-  uint4 sq[SQE];  // x = slot << 16 | y - dbase, y = fixed-point score (0 = dropped), z unused, w = cut | len << 16
-  ShortTables ss;
-  RComp qrow[C::QB];     // staged components of the tile
-  uint2 cur[C::QB];      // list cursor of each staged component: {position, vector id at it}
-  uint8_t cqi[C::QB];    // query slot of each staged component
+  // the per-tile fields first: at small offsets, so that reads of them at
+  // fixed addresses share one base register (the address offset a
+  // local-memory instruction carries is 16 bits)
   int64_t qoff[C::QT + 1];
   float qmw[C::QT];
   float qpn[C::QT];  // bound on the query's part in the corpus rows' unindexed dimensions
@@ -140,6 +127,22 @@ struct Smem {
   int32_t slot;    // range slot of the current item in its queue
   int64_t item;
   unsigned long long cnt[C_NUM];
+  uint32_t acc[C::QT * C::CB];
+  float qd[C::QT * C::RD];
+  Seg seg[C::QB];
+  int32_t segpre[C::QB + 1];
+  // the short stream's tables
+  struct ShortTables {
+    uint8_t flag[C::NT / 64][C::U][64];  // segment-start flags: one row per wave and chunk of a batch
+    uint16_t first[C::QB * (kLongSeg - 1) / 64 + 2];  // segment holding each 64-entry chunk's first entry
+  };
+  // survivor queue entries: the configured capacity less the tables' room
+  static constexpr int SQE = C::SQ - (int)((sizeof(ShortTables) + 15) / 16);
+  uint4 sq[SQE];  // x = slot << 16 | y - dbase, y = fixed-point score (0 = dropped), z unused, w = cut | len << 16
+  ShortTables ss;
+  RComp qrow[C::QB];     // staged components of the tile
+  uint2 cur[C::QB];      // list cursor of each staged component: {position, vector id at it}
+  uint8_t cqi[C::QB];    // query slot of each staged component
 };
 
 // Orders the LDS accesses of one wave around an exchange between its lanes
