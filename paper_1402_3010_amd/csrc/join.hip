@@ -349,15 +349,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   };
 
 
-  // Every entry of the short segments sseg[0..ns) (exclusive prefix sums of
-  // their lengths in sm.segpre, L entries in all): wave w takes a contiguous
-  // slice, 64 consecutive entries per load (lane l, entry c + l), U loads in
-  // flight per lane.  The segment of each entry: lane j holds the start of
-  // the j-th segment after the one holding the chunk's first entry, flags
-  // that start in a per-wave LDS row, and every lane counts the flags at or
-  // before its own entry (one ballot).  Segments are never empty, so at most
-  // 63 of them start inside a chunk.
-  // add(qi, packed entry, query weight).
   // Exclusive prefix sums of the lengths of sseg[0..ns) into sm.segpre (KMAX
   // consecutive segments per thread), and for every 64-entry chunk of the
   // concatenated segments the segment that holds its first entry.  Ends
@@ -405,7 +396,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   // its own entry (one ballot).  Segments are never empty, so at most 63 of
   // them start inside a chunk.  A flag holds the batch's tag, so older flags
   // need no clearing.  The chunks of a batch are independent, so their LDS
-  // round trips overlap.  add(qi, packed entry, query weight).
+  // round trips overlap.  add(qi, packed entry, query weight, live) is
+  // called by every lane; live is false for lanes past the wave's slice,
+  // whose segment, slot and (bounds-checked) load are still valid.
   auto stream_short = [&](const Seg* sseg, int ns, int L, auto&& add) {
     const int per = (((L + NW - 1) / NW) + 63) & ~63;
     const int vbeg = wave * per;
@@ -430,6 +423,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       wave_lds_sync();
       uint32_t pos[U], qwb[U];
       int qs[U];
+      bool lv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int c = base + u * 64;
@@ -442,7 +436,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         const int v = c + lane;
         pos[u] = S.pos + (uint32_t)(v - sm.segpre[sg]);
         qwb[u] = S.q;
-        qs[u] = v < vend ? (int)(S.lenq >> 16) : -1;
+        // lanes past the slice keep a valid segment (sg < ns) and slot
+        qs[u] = (int)(S.lenq >> 16);
+        lv[u] = v < vend;
       }
       wave_lds_sync();
       uint32_t pv[U];
@@ -450,7 +446,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       for (int u = 0; u < U; ++u) pv[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, (int)(pos[u] * 4u), 0, 0);
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (qs[u] >= 0) add(qs[u], pv[u], qwb[u]);
+        add(qs[u], pv[u], qwb[u], lv[u]);
     }
   };
 
@@ -564,7 +560,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     const int L = uni(sm.segpre[ns]);
     if (tid == 0) c_visit += (unsigned long long)L;
     // every entry of every segment, split evenly over the waves
-    stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw) {
+    stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw, bool live) {
+      if (!live) return;
       const uint32_t key = (((uint32_t)qi << 16) | ((p - (uint32_t)rbeg) & 0xFFFFu)) + 1u;
       uint32_t h = (key * 0x9E3779B1u) >> (32 - HBITS);
       for (;;) {
@@ -917,8 +914,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       }
       // short segments: each wave takes a contiguous range of their visits;
       // every lane keeps U list loads in flight
-      stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw) {
-        atomicAdd(&sm.acc[qi * CB + (int)(p & (CB - 1))], packed_product(qw, p));
+      stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw, bool live) {
+        // a lane past the slice adds zero to a slot of its row (no branch)
+        atomicAdd(&sm.acc[qi * CB + (int)(p & (CB - 1))], live ? packed_product(qw, p) : 0u);
       });
       // long segments: wave w takes segments w, w + NW, ... in chunks of 64
       // entries (one per lane).  Lane i holds the descriptor of the wave's
