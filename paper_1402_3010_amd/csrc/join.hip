@@ -135,6 +135,7 @@ struct Smem {
   struct ShortTables {
     uint8_t flag[C::NT / 64][C::U][64];  // segment-start flags: one row per wave and chunk of a batch
     uint16_t first[C::QB * (kLongSeg - 1) / 64 + 2];  // segment holding each 64-entry chunk's first entry
+    uint8_t sink[64];  // flag writes of lanes that have none (never read)
   };
   // survivor queue entries: the configured capacity less the tables' room
   static constexpr int SQE = C::SQ - (int)((sizeof(ShortTables) + 15) / 16);
@@ -415,11 +416,15 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         const int c = base + u * 64;
         sa[u] = c < vend ? (int)sm.ss.first[c >> 6] : 0;
         const int sj = sa[u] + 1 + lane;
-        rel[u] = (c < vend && sj < ns) ? sm.segpre[sj] - c : 0x7FFFFFFF;  // >= 1: segment sa holds entry c
+        // (read at sj clamped to ns, where the total is, so without a branch)
+        const int d = sm.segpre[sj < ns ? sj : ns] - c;
+        rel[u] = (c < vend && sj < ns) ? d : 0x7FFFFFFF;  // >= 1: segment sa holds entry c
       }
+      // every lane stores: a lane whose segment does not start in the chunk
+      // writes to the sink instead of branching around the store
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if ((uint32_t)rel[u] < 64u) sm.ss.flag[wave][u][rel[u]] = (uint8_t)tag;
+        *((uint32_t)rel[u] < 64u ? &sm.ss.flag[wave][u][rel[u]] : &sm.ss.sink[lane]) = (uint8_t)tag;
       wave_lds_sync();
       uint32_t pos[U], qwb[U];
       int qs[U];
