@@ -141,6 +141,11 @@ struct Smem {
   static constexpr int SQE = C::SQ - (int)((sizeof(ShortTables) + 15) / 16);
   uint4 sq[SQE];  // x = slot << 16 | y - dbase, y = fixed-point score (0 = dropped), z unused, w = cut | len << 16
   ShortTables ss;
+  // per-lane targets of the segment placement's stores that have nothing to
+  // place (never read)
+  Seg seg_sink[64];
+  int32_t pre_sink[64];
+  uint16_t first_sink[64];
   RComp qrow[C::QB];     // staged components of the tile
   uint2 cur[C::QB];      // list cursor of each staged component: {position, vector id at it}
   uint8_t cqi[C::QB];    // query slot of each staged component
@@ -872,17 +877,21 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         sseg = sm.seg + (QB - ns);
         const uint32_t ec = wc + icnt - cnt;
         int lb = (int)(ec >> 16), sb = (int)(ec & 0xFFFFu), lp = (int)(wl + ilen - len);
+        // without branches: every component stores its segment, prefix sum
+        // and chunk-table entry, to a sink slot when it has none.  A short
+        // segment holds fewer than 64 entries, so at most one chunk starts
+        // inside it.
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) {
-          if (sk[j] == 2) sm.seg[lb++] = sgj[j];
-          if (sk[j] == 1) {
-            const int sl = (int)(sgj[j].lenq & 0xFFFFu);
-            sseg[sb] = sgj[j];
-            sm.segpre[sb] = lp;
-            for (int c = (lp + 63) & ~63; c < lp + sl; c += 64) sm.ss.first[c >> 6] = (uint16_t)sb;
-            ++sb;
-            lp += sl;
-          }
+          const bool isl = sk[j] == 2, iss = sk[j] == 1;
+          const int sl = iss ? (int)(sgj[j].lenq & 0xFFFFu) : 0;
+          *(isl ? &sm.seg[lb] : (iss ? &sseg[sb] : &sm.seg_sink[lane])) = sgj[j];
+          *(iss ? &sm.segpre[sb] : &sm.pre_sink[lane]) = lp;
+          const int c = (lp + 63) & ~63;
+          *((iss && c < lp + sl) ? &sm.ss.first[c >> 6] : &sm.first_sink[lane]) = (uint16_t)sb;
+          lb += isl ? 1 : 0;
+          sb += iss ? 1 : 0;
+          lp += sl;
         }
         if (tid == 0) sm.segpre[ns] = L;
       }
