@@ -363,7 +363,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the join runs on a single MI355X; "
-              "multi-GPU sharding is not built (see DESIGN.md)", file=sys.stderr)
+              "multi-GPU sharding is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
