@@ -1018,8 +1018,12 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       __syncthreads();
     }
 
-    for (bool first = true;; first = false) {
-      if (!first) load_rows(0);
+    // A full block (every row inside the corpus and, in a self-join, before
+    // the tile's first query) pairs every row with every slot: its copy of
+    // the row loop has no per-slot limit to apply.
+    const bool full_block = blk1 == blk0 + CB && (!a.triangle || blk0 + CB <= q0);
+    auto filter_rows = [&](auto full_t) {
+      constexpr bool FULL = decltype(full_t)::value;
 #pragma unroll 1
       for (int yi = 0; yi < YPT; ++yi) {
         const RowStat st = stN;
@@ -1030,11 +1034,13 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         // query slots qi >= qlo pair with this row: the triangle keeps the
         // pairs whose corpus row precedes the query
         int qlo = 0;
-        if (y >= blk1) {
-          qlo = QT;
-        } else if (a.triangle) {
-          const int64_t d = y - q0 + 1;
-          qlo = d <= 0 ? 0 : (d >= QT ? QT : (int)d);
+        if constexpr (!FULL) {
+          if (y >= blk1) {
+            qlo = QT;
+          } else if (a.triangle) {
+            const int64_t d = y - q0 + 1;
+            qlo = d <= 0 ? 0 : (d >= QT ? QT : (int)d);
+          }
         }
         const uint32_t packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) |
                                 ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
@@ -1049,7 +1055,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 #pragma unroll
         for (int qi = 0; qi < QT; ++qi) {
           const float4 qb = sm.qb[qi];
-          const bool live = (av[qi] != 0u) & (qi >= qlo);
+          const bool live = FULL ? (av[qi] != 0u) : ((av[qi] != 0u) & (qi >= qlo));
           const float A = (float)av[qi];  // accumulator units, as the bounds
           const bool want = live & (ylf * qb.y >= qb.x) & (A + min_nonneg(cutf * qb.y, qb.z) * st.pmw >= qb.x) &
                             (A + qb.w * st.pnrm >= qb.x);
@@ -1084,6 +1090,11 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         for (int qi = 0; qi < QT; ++qi) sm.acc[qi * CB + yl] = ((keep >> qi) & 1u) ? av[qi] : 0u;
         c_cand += ncand;
       }
+    };
+    for (bool first = true;; first = false) {
+      if (!first) load_rows(0);
+      if (full_block) filter_rows(std::integral_constant<bool, true>{});
+      else filter_rows(std::integral_constant<bool, false>{});
       __syncthreads();
       const int o = uni(sm.ovf);
       const int qc = uni(sm.qcount);
