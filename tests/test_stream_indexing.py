@@ -10,6 +10,10 @@ before it.  Lanes past the wave's slice still run the whole sequence and
 must land on a valid segment, since they read it and add zero.  This model
 checks, over random segment layouts, that every live lane finds the segment
 that holds its entry and that every lane reads a segment in range.
+
+A second model covers the block path's segment placement, which stores
+without branches too: long segments fill the front of the segment array,
+short ones its back, and the prefix sums and chunk table agree with them.
 """
 import numpy as np
 import pytest
@@ -98,3 +102,73 @@ def test_short_segments_start_at_most_one_chunk():
             c = (s0 + 63) & ~63
             starts = len(range(c, s0 + sl, 64))
             assert starts == (1 if c < s0 + sl else 0)
+
+
+def place(kinds, lens, QB, KMAX, NT):
+    """The block path's placement: thread t owns components t*KMAX..t*KMAX+KMAX-1
+    in the scan (component j*NT + t in the tile); an exclusive scan over the
+    threads of (long count, short count, short entries) gives each its
+    offsets; long segments fill seg[0..nl), short ones seg[QB-ns..QB), with
+    their prefix sums and one chunk-table entry each."""
+    # per-thread totals in thread order, as the wave scans compute them
+    cnt_l = np.zeros(NT, dtype=np.int64)
+    cnt_s = np.zeros(NT, dtype=np.int64)
+    len_s = np.zeros(NT, dtype=np.int64)
+    for t in range(NT):
+        for j in range(KMAX):
+            k = j * NT + t
+            cnt_l[t] += kinds[k] == 2
+            cnt_s[t] += kinds[k] == 1
+            len_s[t] += lens[k] if kinds[k] == 1 else 0
+    nl, ns, L = int(cnt_l.sum()), int(cnt_s.sum()), int(len_s.sum())
+    ex_l = np.concatenate([[0], np.cumsum(cnt_l)[:-1]])
+    ex_s = np.concatenate([[0], np.cumsum(cnt_s)[:-1]])
+    ex_len = np.concatenate([[0], np.cumsum(len_s)[:-1]])
+    sbase = QB - ns
+    seg = np.full(QB, -1, dtype=np.int64)  # component placed at each slot
+    segpre = np.full(QB + 1, -1, dtype=np.int64)
+    first = {}
+    for t in range(NT):
+        lb, sb, lp = int(ex_l[t]), int(ex_s[t]), int(ex_len[t])
+        for j in range(KMAX):
+            k = j * NT + t
+            isl, iss = kinds[k] == 2, kinds[k] == 1
+            sl = int(lens[k]) if iss else 0
+            if isl or iss:  # (the kernel stores the rest to sinks)
+                idx = lb if isl else sbase + sb
+                assert seg[idx] == -1
+                seg[idx] = k
+            if iss:
+                segpre[sb] = lp
+                c = (lp + 63) & ~63
+                if c < lp + sl:
+                    assert (c >> 6) not in first
+                    first[c >> 6] = sb
+            lb += isl
+            sb += iss
+            lp += sl
+    segpre[ns] = L
+    return seg, segpre, first, nl, ns, L
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("QB,NT", [(1024, 512), (1536, 512), (1024, 256)])
+def test_block_path_placement(seed, QB, NT):
+    rng = np.random.default_rng(7 * seed + QB + NT)
+    KMAX = QB // NT
+    for _ in range(20):
+        kinds = rng.choice([0, 1, 2], size=QB, p=rng.dirichlet([1, 1, 1]))
+        lens = np.where(kinds == 1, rng.integers(1, LONG_SEG, size=QB), rng.integers(LONG_SEG, 5000, size=QB))
+        seg, segpre, first, nl, ns, L = place(kinds, lens, QB, KMAX, NT)
+        longs = set(np.nonzero(kinds == 2)[0])
+        shorts_in_order = [k for t in range(NT) for j in range(KMAX) if kinds[(k := j * NT + t)] == 1]
+        # long segments at the front, short ones at the back, none lost or shared
+        assert set(seg[:nl]) == longs and nl + ns <= QB
+        assert list(seg[QB - ns:]) == shorts_in_order
+        assert np.all(seg[nl:QB - ns] == -1)
+        # prefix sums and the chunk table agree with the short segments' lengths
+        sl = np.array([lens[k] for k in shorts_in_order], dtype=np.int64)
+        assert np.array_equal(segpre[:ns + 1], np.concatenate([[0], np.cumsum(sl)]))
+        owner = np.repeat(np.arange(ns), sl)
+        for c in range(0, L, 64):
+            assert first[c >> 6] == owner[c]
