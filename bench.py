@@ -41,8 +41,52 @@ WORKLOADS = {
 }
 
 
+# The paper's own figures for context (Tables 2-4).  They are sequential CPU
+# wall times of its OCaml 3.12 implementation with 32-bit fixed-point weights
+# (Section 7.2), on its two small text datasets (radikal: 6,883 vectors,
+# 1,072,472 non-zeros; 20-newsgroups: 20,001 vectors, 2,984,809 non-zeros)
+# and, in Table 4, on the five problem instances.  The hardware of Tables 2
+# and 3 is not stated; Table 4 ran on the AMD Opteron 6172 (48-core nodes)
+# cluster of Section 7.4.  No time unit is printed (presumably seconds).
+# None of these is the metric measured here: the paper reports no GPU
+# numbers, no candidate-pair rates and no serving latency.
+PAPER_FIGURES = {
+    "implementation": "OCaml 3.12, sequential, 32-bit fixed-point weights (Section 7.2)",
+    "units": "unstated (presumably seconds)",
+    "table2_radikal": {
+        "hardware": "not stated", "t": [0.2, 0.3, 0.4],
+        "times": {"all-pairs-0-array": [24.57, 24.44, 24.74], "all-pairs-1": [87.10, 79.05, 71.73],
+                  "all-pairs-1-array": [73.02, 69.54, 64.40], "all-pairs-1-remscore": [180.55, 181.79, 182.02],
+                  "all-pairs-1-upperbound": [200.96, 171.42, 145.90], "all-pairs-1-minsize": [89.57, 80.52, 72.21],
+                  "all-pairs-2": [198.92, 165.64, 138.98], "all-pairs-bruteforce": [183.06, 183.32, 183.28]}},
+    "table3_20newsgroups": {
+        "hardware": "not stated", "t": [0.4, 0.5, 0.6],
+        "times": {"all-pairs-0-array": [480.0, 495.4, 478.0], "all-pairs-1": [1169.0, 1035.6, 882.9],
+                  "all-pairs-1-array": [883.8, 837.0, 757.5], "all-pairs-1-remscore": [3502.0, 3499.9, 3497.7],
+                  "all-pairs-2": [1733.8, 1450.0, 1190.2], "all-pairs-bruteforce": [1866.3, 1867.2, 1871.5]}},
+    "table4_problem_instances": {
+        "hardware": "AMD Opteron 6172 cluster nodes, one core (Section 7.4)", "algorithm": "all-pairs-0-array",
+        "rows": [{"dataset": "radikal", "t": 0.2, "time": 15.5, "matches": 16810},
+                 {"dataset": "20-newsgroups", "t": 0.4, "time": 317.3, "matches": 64396},
+                 {"dataset": "wikipedia", "t": 0.9, "time": 54424.0, "matches": 747999},
+                 {"dataset": "facebook", "t": 0.99, "time": 10777.8, "matches": 819196},
+                 {"dataset": "virginia-tech", "t": 0.99, "time": 10426.2, "matches": 13447874}]},
+}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(V, t, budget_s: float):
@@ -72,6 +116,7 @@ def cpu_baseline(V, t, budget_s: float):
         "value": r.candidates / dt,
         "unit": "candidate pairs scored/s",
         "cores": oracle.num_threads(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": "rows %d..%d of the same corpus, each against all earlier rows: %d candidate pairs, "
                   "%d matches in %.1f s (includes building the full inverted index)"
@@ -101,6 +146,20 @@ def measured_traffic(config, t, n):
     if rec.get("source_hash") != kernel_source_hash() or abs(rec.get("t", -1) - float(t)) > 1e-6:
         return None
     return rec["traffic_bytes"]
+
+
+def measured_counters(config, t, n):
+    """Issue and LDS figures of the k_join dispatch from the committed counter
+    summary, if it was taken on this workload at full size and on the kernel
+    source as it is now."""
+    path = os.path.join(ROOT, "profiles", "k_join_%s_counters.json" % config)
+    if n is not None or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash() or abs(rec.get("t", -1) - float(t)) > 1e-6:
+        return None
+    return rec
 
 
 def percentile(x, q):
@@ -424,11 +483,16 @@ def main():
     ms_step = 1000.0 * elapsed / args.steps
     cand = stats["candidates"]
     value = cand / (ms_step / 1000.0)
-    # algorithmic bytes of the candidate kernel: 8 B per posting visit, 8 B per
-    # query component read, 12 B per emitted pair
-    alg_bytes = 8.0 * stats["posting_visits"] + 8.0 * V.nnz + 12.0 * stats["matches"]
+    # algorithmic bytes of the candidate kernel: the 4-byte packed list entry
+    # it streams per posting visit, 8 B per query component read, 12 B per
+    # emitted pair.  (The survey's convention counts 8 B per visit, an id and
+    # a float weight; that figure is reported beside it.)
+    alg_bytes = 4.0 * stats["posting_visits"] + 8.0 * V.nnz + 12.0 * stats["matches"]
+    alg_bytes_8b = alg_bytes + 4.0 * stats["posting_visits"]
     kms = sum(kern_ms) / len(kern_ms)
     achieved = alg_bytes / (kms / 1000.0) / 1e9
+    traffic = measured_traffic(args.config, t, args.n)
+    counters = measured_counters(args.config, t, args.n)
     out = {
         "metric": "candidate pairs scored/s and matches/s at 1M vectors t=0.7; serve p50/p99 latency",
         "value": value,
@@ -456,9 +520,17 @@ def main():
         "tuning": tune,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": measured_traffic(args.config, t, args.n),
+                     "traffic": traffic,
+                     "frac_dram": (traffic / (kms / 1000.0) / 1e9 / PEAK_HBM_GBS) if traffic else None,
+                     "frac_8b_per_visit": alg_bytes_8b / (kms / 1000.0) / 1e9 / PEAK_HBM_GBS,
+                     "binding_unit": counters.get("binding_unit") if counters else None,
+                     "issue": ({k: counters[k] for k in ("valu_issue_frac", "salu_issue_frac", "lds_bank_conflict_frac")
+                                if k in counters} if counters else None),
                      "kernel": "k_join", "kernel_ms": kms, "algorithmic_bytes": alg_bytes,
-                     "traffic_source": "profiles/k_join_%s_traffic.md" % args.config},
+                     "algorithmic_bytes_8b_per_visit": alg_bytes_8b,
+                     "traffic_source": "profiles/k_join_%s_traffic.md" % args.config,
+                     "counters_source": "profiles/k_join_%s_counters.md" % args.config},
+        "paper_figures": PAPER_FIGURES,
     }
     ix.close()
     if not args.no_cpu_baseline:

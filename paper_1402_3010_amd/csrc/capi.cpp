@@ -762,6 +762,12 @@ int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, in
 
 namespace {
 
+// Pair capacity a self-join starts with (grows on overflow, which reruns
+// the join kernel): 32 pairs per vector, 384 MB of pair buffers per million
+// vectors, which holds the matches of the million-vector workloads at their
+// thresholds (about 22 per vector at t = 0.7) on the first call.
+int64_t join_cap_hint(const apss_index* ix) { return std::max<int64_t>(1 << 20, 32 * ix->n); }
+
 std::vector<const void*> graph_buffers(const apss_index* ix, const Workspace& ws) {
   return {ws.tstart.p, ws.qcum.p, ws.qctr.p, ws.counters.p, ws.wg_cur.p, ws.raw_key.p, ws.raw_sim.p, ws.ss.k2.p,
           ws.ss.v32b.p, ws.ss.hist.p, ws.ss.scan.p, ix->toff.p, ix->hoff[0].p, ix->hoff[1].p,
@@ -847,7 +853,7 @@ int graph_join(apss_index* ix, float t, uint32_t* out_i, uint32_t* out_j, float*
   int64_t cnt = 0;
   if ((rc = run_join(ix, ws, QuerySet{ix->rows.rp.p, ix->rows.rc.p, ix->rows.mw.p, ix->n, ix->nnz,
                                       ix->rows.rp_host.data()},
-                     1, t, nullptr, std::max<int64_t>(1 << 20, 16 * ix->n), &cnt)))
+                     1, t, nullptr, join_cap_hint(ix), &cnt)))
     return rc;
   if ((rc = finish_device(ws, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count))) return rc;
   const apss_stats keep = ws.last;
@@ -1056,9 +1062,6 @@ QuerySet corpus_queries(const apss_index* ix) {
 QuerySet staged_queries(const RankRows& r) {
   return QuerySet{r.rp.p, r.rc.p, r.mw.p, r.n, r.nnz, r.rp_host.data()};
 }
-
-// Pair capacity a self-join starts with (grows on overflow).
-int64_t join_cap_hint(const apss_index* ix) { return std::max<int64_t>(1 << 20, 16 * ix->n); }
 
 int self_join(apss_index* ix, float t, int64_t* cnt) {
   if (ix->screen) return run_screen_join(ix, ix->ws, t, join_cap_hint(ix), cnt);

@@ -42,9 +42,19 @@ namespace apss {
 
 namespace {
 
-// q_d * y_d in 2^-30 units, rounded up (the product is at most 1, so the
-// scaled value is exact in float and below 2^30 + 1)
-__device__ __forceinline__ uint32_t fixp(float a, float b) { return (uint32_t)ceilf(__fmul_rn(a, b) * kFix); }
+// q_d * y_d in 2^-30 units, rounded up: an upper bound of the exact
+// product.  The float product p is rounded to nearest; the fused multiply-add
+// gives its exact residual a*b - p, and when that is positive p is replaced
+// by the next float above it, which is at least a*b.  Scaling by 2^30 is
+// exact (p <= 1), so the ceiling bounds a*b * 2^30 from above.  Both weights
+// are positive, so a product that underflows still counts one unit.
+__device__ __forceinline__ uint32_t fixp(float a, float b) {
+  const float p = __fmul_rn(a, b);
+  const float e = __builtin_fmaf(a, b, -p);
+  const float pu = e > 0.0f ? __uint_as_float(__float_as_uint(p) + 1u) : p;
+  const uint32_t v = (uint32_t)ceilf(pu * kFix);
+  return v > 0u ? v : 1u;
+}
 
 // Query weight in units of 2^-15, rounded up.  A packed list entry holds the
 // corpus weight in the same units (bits 16..31, rounded up) and the vector id

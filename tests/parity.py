@@ -41,3 +41,36 @@ def assert_parity(gi, gj, gs, ref, t, V, W=None, per_row_t=None):
         d = max(abs(G[k] - O[k]) for k in common)
         assert d <= SIM_TOL, "sim error %g" % d
     return len(common), len(only_g), len(only_o)
+
+
+def assert_rows_parity(gi, gj, gs, V, t, rows, oracle):
+    """Self-join pairs (gi, gj, gs) against the oracle on every pair that
+    involves one of `rows` (as i or as j), whatever its partner.
+
+    The oracle finds the partners of each selected row by the plain
+    definition over the whole corpus (query mode), so the check does not
+    depend on how the rows were chosen.  Returns the number of pairs compared.
+    """
+    rows = np.unique(np.asarray(rows, np.int64))
+    ref = oracle.query(V, V.take_rows(rows), t=float(t))
+    O = {}
+    for q, y, s in zip(ref.i.tolist(), ref.j.tolist(), ref.s.tolist()):
+        r = int(rows[q])
+        if r == y:
+            continue
+        O[(min(r, y) << 32) | max(r, y)] = s
+    gi = np.asarray(gi, np.int64)
+    gj = np.asarray(gj, np.int64)
+    sel = np.isin(gi, rows) | np.isin(gj, rows)
+    gk = (gi[sel] << 32) | gj[sel]
+    G = dict(zip(gk.tolist(), np.asarray(gs, np.float64)[sel].tolist()))
+    for k in set(G) - set(O):
+        s = exact_dot(V, k >> 32, k & 0xFFFFFFFF)
+        assert abs(s - t) <= BAND, "extra pair %s sim %.9f t %.9f" % ((k >> 32, k & 0xFFFFFFFF), s, t)
+    for k in set(O) - set(G):
+        assert abs(O[k] - t) <= BAND, "missing pair %s sim %.9f t %.9f" % ((k >> 32, k & 0xFFFFFFFF), O[k], t)
+    common = set(G) & set(O)
+    if common:
+        d = max(abs(G[k] - O[k]) for k in common)
+        assert d <= SIM_TOL, "sim error %g" % d
+    return len(common)
