@@ -103,6 +103,28 @@ void apss_index_free(apss_index* idx);
 int apss_join_device(apss_index* idx, float t, uint32_t* out_i, uint32_t* out_j, float* out_sim,
                      int64_t capacity, int64_t* count);
 
+/* Allocation-free self-join, for callers that cannot allocate device
+ * memory during the call: code under HIP stream capture, tight serving
+ * loops, harnesses that forbid allocation.  Same contract and result as
+ * apss_join_device on an index built without screen_dims, on the index's
+ * stream and device (current at the call).  Every scratch buffer of the call
+ * (work queues and counters, per-workgroup list cursors, raw pairs, sort
+ * scratch) is placed in one fixed device array of
+ * APSS_NOALLOC_SCRATCH_BYTES bytes, which the library holds on each device it
+ * runs on until the process ends; the index's join tables are made by
+ * apss_build_index (and remade by apss_autotune), so the call allocates
+ * nothing.  All calls on one device share that device's array: calls that
+ * overlap on one device (from several threads, streams or indexes) race and
+ * must not be made.
+ * Errors: as apss_join_device; APSS_EINVAL also for a screened index, a call
+ * on another device than the index's, or an index whose tables are not
+ * ready; APSS_ENOMEM when the join needs more scratch than the array holds
+ * (its work queues, or more pairs than fit beside them -- then *count is the
+ * number of pairs; apss_join_device has no such limit). */
+#define APSS_NOALLOC_SCRATCH_BYTES (128ll << 20)
+int apss_join_device_noalloc(apss_index* idx, float t, uint32_t* out_i, uint32_t* out_j, float* out_sim,
+                             int64_t capacity, int64_t* count);
+
 /* Pairs in library-owned host memory; free with apss_pairs_free. */
 typedef struct {
   int64_t count;

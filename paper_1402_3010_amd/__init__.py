@@ -29,6 +29,7 @@ APSS_EDEVICE = 4
 APSS_ERANGE = 5
 APSS_EBUSY = 6
 APSS_PENDING = 100
+NOALLOC_SCRATCH_BYTES = 128 << 20  # APSS_NOALLOC_SCRATCH_BYTES of include/apss.h
 
 
 class ApssError(RuntimeError):
@@ -111,6 +112,8 @@ def load(path: str = LIB_PATH):
     lib.apss_index_free.restype = None
     lib.apss_join_device.argtypes = [P, f32, P, P, P, i64, ctypes.POINTER(i64)]
     lib.apss_join_device.restype = ctypes.c_int
+    lib.apss_join_device_noalloc.argtypes = [P, f32, P, P, P, i64, ctypes.POINTER(i64)]
+    lib.apss_join_device_noalloc.restype = ctypes.c_int
     lib.apss_join.argtypes = [P, f32, ctypes.POINTER(Pairs)]
     lib.apss_join.restype = ctypes.c_int
     lib.apss_query.argtypes = [P, i64, P, P, P, ctypes.c_int, P, f32, ctypes.POINTER(Pairs)]
@@ -150,7 +153,8 @@ def load(path: str = LIB_PATH):
     return lib
 
 
-EXPORTED = ("apss_default_opts", "apss_build_index", "apss_index_free", "apss_join_device", "apss_join",
+EXPORTED = ("apss_default_opts", "apss_build_index", "apss_index_free", "apss_join_device",
+            "apss_join_device_noalloc", "apss_join",
             "apss_query", "apss_query_device", "apss_pairs_free", "apss_last_stats", "apss_index_export",
             "apss_index_sizes", "apss_strerror", "apss_last_error", "apss_autotune", "apss_server_default_opts",
             "apss_server_create", "apss_submit", "apss_poll", "apss_server_pause", "apss_server_stats",
@@ -263,6 +267,20 @@ def join_device(h: int, t: float, out_i, out_j, out_sim) -> int:
     return cnt.value
 
 
+def join_device_noalloc(h: int, t: float, out_i, out_j, out_sim) -> int:
+    """apss_join_device_noalloc: join_device with every scratch buffer in the
+    library's fixed device array (no allocation during the call)."""
+    cnt = ctypes.c_int64()
+    rc = load().apss_join_device_noalloc(h, float(t), out_i.data_ptr(), out_j.data_ptr(), out_sim.data_ptr(),
+                                         int(out_i.numel()), ctypes.byref(cnt))
+    if rc in (APSS_ERANGE, APSS_ENOMEM):
+        e = ApssError(rc, last_error())
+        e.count = cnt.value
+        raise e
+    _check(rc)
+    return cnt.value
+
+
 def _query_args(Q_row_ptr, Q_col, Q_val, t_per_row):
     ptrs, on_dev, keep = _csr_args(Q_row_ptr, Q_col, Q_val)
     if t_per_row is not None:
@@ -351,6 +369,9 @@ class Index:
 
     def join_device(self, t: float, out_i, out_j, out_sim) -> int:
         return join_device(self.handle, t, out_i, out_j, out_sim)
+
+    def join_device_noalloc(self, t: float, out_i, out_j, out_sim) -> int:
+        return join_device_noalloc(self.handle, t, out_i, out_j, out_sim)
 
     def query(self, Q, t: float = 0.0, t_per_row=None):
         return query(self.handle, Q.n, Q.row_ptr, Q.col, Q.val, t, t_per_row)

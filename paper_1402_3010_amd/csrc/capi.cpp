@@ -356,11 +356,6 @@ int build_screen(apss_index* ix, int32_t head) {
 
 // Query tiles: consecutive queries, at most QT of them and, unless a single
 // query is larger, at most QB components, so that a tile fits the LDS staging.
-struct Tiles {
-  std::vector<int64_t> start;  // ntiles + 1 entries
-  int64_t max_nnz = 0;
-};
-
 Tiles make_tiles(const int64_t* rp, int64_t n, int QT, int QB) {
   Tiles T;
   T.start.push_back(0);
@@ -425,62 +420,47 @@ int prepare(apss_index* ix, hipStream_t s, int variant, int64_t range_rows) {
   return APSS_OK;
 }
 
-// Host-side preparation of one join kernel launch: tiles, work queues and
-// cursor space on ws's stream.  Output buffers and counters are set at launch.
-struct JoinPlan {
-  JoinArgs a{};
-  int variant = 0;
-  int G = 0;
-  int bi = 0, bj = 0;
-};
-
-int plan_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, float t, const float* qt_dev,
-              const RowStat* qrs, JoinPlan& P) {
-  hipStream_t s = ws.stream;
+int plan_layout(apss_index* ix, const QuerySet& Q, int triangle, JoinLayout& L) {
   const int variant = ix->variant;
-  int QT = 0, CB = 0;
-  if (join_variant_geometry(variant, &QT, &CB)) {
+  if (join_variant_geometry(variant, &L.QT, &L.CB)) {
     set_error("unknown join variant %d", variant);
     return APSS_EINVAL;
   }
-  int rc0 = prepare(ix, s, variant, ix->range_rows);
-  if (rc0) return rc0;
-  const int slot = hoff_slot(CB);
-  const int64_t nb = ix->hoff_nb[slot];
+  L.variant = variant;
+  L.slot = hoff_slot(L.CB);
+  L.nb = ix->hoff_nb[L.slot];
   // work items: ranges of K blocks x query tiles
   const int64_t range_rows = ix->toff_rows;
-  const int K = (int)(range_rows / CB);
-  const int64_t nR = ix->toff_nR;
-  const Tiles tiles = make_tiles(Q.rp_host, Q.n, QT, join_variant_staging(variant));
-  const int64_t ntiles = (int64_t)tiles.start.size() - 1;
-  CHK(ws.tstart.reserve(ntiles + 1), "alloc tiles");
-  CHK(hipMemcpyAsync(ws.tstart.p, tiles.start.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, s),
-      "tiles");
-  const int64_t nrx = (nR + 7) / 8;
-  std::vector<int64_t> cum((size_t)(8 * (nrx + 1)), 0);
+  L.K = (int)(range_rows / L.CB);
+  L.nR = ix->toff_nR;
+  L.tiles = make_tiles(Q.rp_host, Q.n, L.QT, join_variant_staging(variant));
+  L.ntiles = (int64_t)L.tiles.start.size() - 1;
+  L.nrx = (L.nR + 7) / 8;
+  L.cum.assign((size_t)(8 * (L.nrx + 1)), 0);
   for (int x = 0; x < 8; ++x) {
     int64_t c = 0;
-    for (int64_t j = 0; j <= nrx; ++j) {
-      cum[(size_t)(x * (nrx + 1) + j)] = c;
+    for (int64_t j = 0; j <= L.nrx; ++j) {
+      L.cum[(size_t)(x * (L.nrx + 1) + j)] = c;
       const int64_t R = x + 8 * j;
-      if (j < nrx && R < nR) {
+      if (j < L.nrx && R < L.nR) {
         // first tile whose last query reaches the range (self-join triangle)
         const int64_t tmin =
-            triangle ? (int64_t)(std::upper_bound(tiles.start.begin() + 1, tiles.start.end(), R * range_rows) -
-                                 (tiles.start.begin() + 1))
+            triangle ? (int64_t)(std::upper_bound(L.tiles.start.begin() + 1, L.tiles.start.end(), R * range_rows) -
+                                 (L.tiles.start.begin() + 1))
                      : 0;
-        c += ntiles - tmin;
+        c += L.ntiles - tmin;
       }
     }
   }
-  CHK(ws.qcum.reserve((int64_t)cum.size()), "alloc queues");
-  CHK(hipMemcpyAsync(ws.qcum.p, cum.data(), sizeof(int64_t) * cum.size(), hipMemcpyHostToDevice, s), "queues");
-  CHK(ws.qctr.reserve(8), "alloc queues");
-  CHK(ws.counters.reserve(C_NUM), "alloc counters");
-  const int G = ix->grid[variant];
+  L.G = ix->grid[variant];
   // per-workgroup cursor space for tiles too large to stage in LDS
-  const int64_t wg_stride = 2 * std::max<int64_t>(tiles.max_nnz, 1);
-  CHK(ws.wg_cur.reserve((int64_t)G * wg_stride), "alloc cursors");
+  L.wg_stride = 2 * std::max<int64_t>(L.tiles.max_nnz, 1);
+  return APSS_OK;
+}
+
+void bind_plan(apss_index* ix, const QuerySet& Q, int triangle, float t, const float* qt_dev, const RowStat* qrs,
+               const JoinLayout& L, const int64_t* tstart_dev, const int64_t* qcum_dev, unsigned int* qctr_dev,
+               uint32_t* wg_cur_dev, JoinPlan& P) {
   JoinArgs& a = P.a;
   a = JoinArgs{};
   a.rp = ix->rows.rp.p;
@@ -490,9 +470,9 @@ int plan_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, fl
   a.post = ix->post.p;
   a.post4 = ix->post4.p;
   a.post4_bytes = (uint32_t)(4 * (ix->P + kPost4Pad));
-  a.hoff = ix->hoff[slot].p;
+  a.hoff = ix->hoff[L.slot].p;
   a.H = ix->H;
-  a.nb = nb;
+  a.nb = L.nb;
   a.n = ix->n;
   a.qrp = Q.rp;
   a.qrc = Q.rc;
@@ -502,21 +482,39 @@ int plan_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, fl
   a.t = t;
   a.nq = Q.n;
   a.triangle = triangle;
-  a.ntiles = ntiles;
-  a.tstart = ws.tstart.p;
+  a.ntiles = L.ntiles;
+  a.tstart = tstart_dev;
   a.toff = ix->toff.p;
   a.m_tail = (int32_t)(ix->m - ix->H);
-  a.K = K;
-  a.nrx = nrx;
-  a.qcum = ws.qcum.p;
-  a.qctr = ws.qctr.p;
-  a.wg_cur = ws.wg_cur.p;
-  a.wg_cur_stride = wg_stride;
-  P.variant = variant;
-  P.G = G;
+  a.K = L.K;
+  a.nrx = L.nrx;
+  a.qcum = qcum_dev;
+  a.qctr = qctr_dev;
+  a.wg_cur = wg_cur_dev;
+  a.wg_cur_stride = L.wg_stride;
+  P.variant = L.variant;
+  P.G = L.G;
   P.bj = ceil_log2((uint64_t)ix->n);
   P.bi = ceil_log2((uint64_t)(triangle ? ix->n : Q.n));
   a.bj = P.bj;
+}
+
+int plan_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, float t, const float* qt_dev,
+              const RowStat* qrs, JoinPlan& P) {
+  hipStream_t s = ws.stream;
+  int rc0 = prepare(ix, s, ix->variant, ix->range_rows);
+  if (rc0) return rc0;
+  JoinLayout L;
+  if ((rc0 = plan_layout(ix, Q, triangle, L))) return rc0;
+  CHK(ws.tstart.reserve(L.ntiles + 1), "alloc tiles");
+  CHK(hipMemcpyAsync(ws.tstart.p, L.tiles.start.data(), sizeof(int64_t) * (L.ntiles + 1), hipMemcpyHostToDevice, s),
+      "tiles");
+  CHK(ws.qcum.reserve((int64_t)L.cum.size()), "alloc queues");
+  CHK(hipMemcpyAsync(ws.qcum.p, L.cum.data(), sizeof(int64_t) * L.cum.size(), hipMemcpyHostToDevice, s), "queues");
+  CHK(ws.qctr.reserve(8), "alloc queues");
+  CHK(ws.counters.reserve(C_NUM), "alloc counters");
+  CHK(ws.wg_cur.reserve((int64_t)L.G * L.wg_stride), "alloc cursors");
+  bind_plan(ix, Q, triangle, t, qt_dev, qrs, L, ws.tstart.p, ws.qcum.p, ws.qctr.p, ws.wg_cur.p, P);
   return APSS_OK;
 }
 
@@ -1149,6 +1147,14 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
   }
   int rc = build_impl(ix, row_ptr, col, val, on_device);
   if (!rc && o.screen_dims > 0) rc = build_screen(ix, (int32_t)std::min<int64_t>(o.screen_dims, m));
+  // the join's lookup tables for the index's geometry and the call timers
+  // exist from here on, so apss_join_device_noalloc needs no allocation
+  if (!rc && o.screen_dims == 0 && n > 0) rc = prepare(ix, ix->ws.stream, ix->variant, ix->range_rows);
+  for (int e = 0; !rc && e < 6; ++e)
+    if (hipEventCreateWithFlags(&ix->ws.ev[e], hipEventDefault) != hipSuccess) {
+      set_error("hipEventCreateWithFlags failed");
+      rc = APSS_EDEVICE;
+    }
   if (rc) {
     (void)hipStreamSynchronize(ix->ws.stream);
     apss_index_free(ix);

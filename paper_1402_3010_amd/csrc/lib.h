@@ -10,6 +10,7 @@
 
 #include "../../include/apss.h"
 #include "apss_internal.h"
+#include "join.h"
 
 namespace apss {
 
@@ -191,6 +192,40 @@ struct QuerySet {
   int64_t n, nnz;
   const int64_t* rp_host;  // host copy of rp
 };
+
+// Query tiles of a join: first query of each tile (ntiles + 1 entries) and
+// the largest tile's component count.
+struct Tiles {
+  std::vector<int64_t> start;
+  int64_t max_nnz = 0;
+};
+
+// Host side of one join kernel launch: geometry, query tiles and the
+// cumulative item counts of the 8 per-XCD work queues.
+struct JoinLayout {
+  int variant = 0, QT = 0, CB = 0, slot = 0, K = 0, G = 0;
+  int64_t nb = 0, nR = 0, nrx = 0, ntiles = 0, wg_stride = 0;
+  Tiles tiles;
+  std::vector<int64_t> cum;  // 8 * (nrx + 1)
+};
+
+// A join kernel launch with every argument but its outputs and counters.
+struct JoinPlan {
+  JoinArgs a{};
+  int variant = 0;
+  int G = 0;
+  int bi = 0, bj = 0;
+};
+
+// Layout of a join of Q against the index (the index's tables for its tile
+// variant and range width must have been made ready by prepare()).
+int plan_layout(apss_index* ix, const QuerySet& Q, int triangle, JoinLayout& L);
+// Kernel arguments of that layout with the given device copies of its tiles
+// (L.ntiles + 1 entries) and queues (L.cum), 8 queue counters and
+// L.G * L.wg_stride cursor words.
+void bind_plan(apss_index* ix, const QuerySet& Q, int triangle, float t, const float* qt_dev, const RowStat* qrs,
+               const JoinLayout& L, const int64_t* tstart_dev, const int64_t* qcum_dev, unsigned int* qctr_dev,
+               uint32_t* wg_cur_dev, JoinPlan& P);
 
 std::string& last_error();  // per calling thread
 void set_error(const char* fmt, ...);

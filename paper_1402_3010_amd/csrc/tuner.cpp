@@ -119,6 +119,9 @@ extern "C" int apss_autotune(apss_index* ix, float t, double budget_ms, const ch
         variant_available(it->second.variant) && it->second.range_rows > 0) {
       target->variant = it->second.variant;
       target->range_rows = it->second.range_rows;
+      // the chosen geometry's tables exist before the next join, which then
+      // allocates none of them
+      if ((rc = prepare(target, ix->ws.stream, target->variant, target->range_rows))) return rc;
       out->variant = it->second.variant;
       out->range_rows = (int32_t)it->second.range_rows;
       out->ms = it->second.ms;
@@ -165,6 +168,7 @@ extern "C" int apss_autotune(apss_index* ix, float t, double budget_ms, const ch
   }
   target->variant = best.variant;
   target->range_rows = best.range_rows;
+  if ((rc = prepare(target, ix->ws.stream, target->variant, target->range_rows))) return rc;
   out->variant = best.variant;
   out->range_rows = (int32_t)best.range_rows;
   out->ms = best.ms;
