@@ -74,7 +74,25 @@ typedef struct {
                             graph and replays it on later calls with the same t and output
                             buffers (one launch, one synchronisation per call); the graph's
                             stats report its whole device time as ms_candidates.  0: default */
-  int32_t reserved[8];
+  int32_t index_all;     /* 1: index every component of every vector (no unindexed part): the
+                            all-pairs-0-array algorithm of Section 4 (Algorithms 1 and 2 with a
+                            dense score array per corpus block), the ablation of partial
+                            indexing; not with screen_dims.  0 (default): partial indexing */
+  int32_t local_parts;   /* p in {2, 4, 8}: local pruning (Section 5.1.3, Eq. 1 and Lemma 1).  The
+                            indexed dimensions are split into p rank ranges of about equal
+                            postings (the densest lists apart from the rest); every work item
+                            scores one range, keeps a candidate only if its local score reaches
+                            the local threshold t/p (with the unindexed part's bound shared
+                            evenly), and the survivors are decided on their exact full score;
+                            a pair kept by several ranges is reported once.  Not with
+                            screen_dims.  0 or 1 (default): off */
+  int32_t remscore;      /* 1: the remscore rule of all-pairs-2 (Section 3.2.2): components of a
+                            query processed rarest first stop admitting new candidates once the
+                            remaining bound sum q[d] * maxweight_d(V) of the components not yet
+                            processed, the current one included, is below t; a candidate all of
+                            whose indexed overlap lies in components past that point is dropped
+                            before the bounds.  0 (default): off */
+  int32_t reserved[5];
 } apss_opts;
 
 void apss_default_opts(apss_opts* opts);

@@ -11,7 +11,8 @@ Functions (each restates a passage of the paper, see apss_oracle.c):
 * ``join_plain``    all-pairs-0-array: Algorithms 1 and 2 with a dense score
                     array (Section 4) -- the plain definition of the match set.
 * ``join_prefix``   all-pairs-1 partial indexing (Section 3.2.2) with the
-                    optional minsize / upperbound tests of all-pairs-2.
+                    optional minsize / remscore / upperbound tests of
+                    all-pairs-2.
 * ``prefix_index``  dimension order, maxweight_i(V) and the unindexed-prefix
                     length of every vector (Section 3.2.2).
 * ``query``         Find-Matches (Algorithm 2) for external query rows.
@@ -33,6 +34,7 @@ _LIB = None
 FLAG_MINSIZE = 1
 FLAG_UPPERBOUND = 2
 FLAG_L2_CLAUSE = 4
+FLAG_REMSCORE = 8
 
 
 class _Result(ctypes.Structure):

@@ -17,8 +17,8 @@
  *   oracle_join_plain    all-pairs-0-array (Algorithms 1 and 2 with a dense
  *                        score array, Section 4): the plain definition;
  *   oracle_join_prefix   all-pairs-1 partial indexing (Section 3.2.2) with
- *                        the optional minsize and upperbound tests of
- *                        all-pairs-2; must return the same set;
+ *                        the optional minsize, remscore and upperbound
+ *                        tests of all-pairs-2; must return the same set;
  *   oracle_prefix_index  the ingredients of partial indexing (dimension
  *                        order, maxweight_i(V), unindexed prefix length);
  *   oracle_query         Find-Matches semantics for external query rows
@@ -355,6 +355,10 @@ int oracle_prefix_index(int64_t n, int64_t m, const int64_t* rp, const int32_t* 
 /*   flags & 2 : upperbound -- skip dot(x, y') when                      */
 /*               A[y] + min(|y'|, |x|) maxweight(x) maxweight(y') < t    */
 /*   flags & 4 : l2 clause in the cutoff (see oracle_prefix_index)      */
+/*   flags & 8 : remscore -- x's components are processed rarest first;  */
+/*               remscore starts at sum_i x[i] maxweight_i(V) and loses  */
+/*               each component's term after it is processed; while it  */
+/*               is below t a y not yet in the map is not added          */
 /* The score is completed as A[y] + dot(x, y').                         */
 /* ------------------------------------------------------------------ */
 int oracle_join_prefix(int64_t n, int64_t m, const int64_t* rp, const int32_t* col, const float* val,
@@ -421,7 +425,12 @@ int oracle_join_prefix(int64_t n, int64_t m, const int64_t* rp, const int32_t* c
       int64_t a = rp[i], len = rp[i + 1] - rp[i];
       /* Find-Matches: every component of x against the lists */
       int64_t ntch = 0;
-      for (int64_t k = 0; k < len; ++k) {
+      double remscore = 0.0;
+      if (flags & 8)
+        for (int64_t k = 0; k < len; ++k) remscore += sw[a + k] * (double)mw[sdim[a + k]];
+      for (int64_t kk = 0; kk < len; ++kk) {
+        /* remscore processes the rarest dimension first */
+        int64_t k = (flags & 8) ? len - 1 - kk : kk;
         int32_t d = sdim[a + k];
         double xw = sw[a + k];
         xdense[d] = xw;
@@ -429,9 +438,14 @@ int oracle_join_prefix(int64_t n, int64_t m, const int64_t* rp, const int32_t* c
           int64_t y = irow[p];
           visits++;
           if ((flags & 1) && (double)(rp[y + 1] - rp[y]) * xmax[i] < t) continue;
-          if (!seen[y]) { seen[y] = 1; touched[ntch++] = y; }
+          if (!seen[y]) {
+            if ((flags & 8) && remscore < t) continue;
+            seen[y] = 1;
+            touched[ntch++] = y;
+          }
           A[y] += xw * iw[p];
         }
+        if (flags & 8) remscore -= xw * (double)mw[d];
       }
       cands += ntch;
       for (int64_t e = 0; e < ntch; ++e) {

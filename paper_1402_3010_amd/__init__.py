@@ -41,8 +41,9 @@ class ApssError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("stream", ctypes.c_void_p), ("query_safe", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("head_dims", ctypes.c_int32), ("range_rows", ctypes.c_int32),
-                ("screen_dims", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("screen_dims", ctypes.c_int32), ("graph", ctypes.c_int32), ("index_all", ctypes.c_int32),
+                ("local_parts", ctypes.c_int32), ("remscore", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class Pairs(ctypes.Structure):
@@ -203,7 +204,8 @@ def current_stream_handle() -> Optional[int]:
 
 
 def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, variant: int = -1,
-                 range_rows: int = 0, screen_dims: int = 0, graph: bool = False) -> Opts:
+                 range_rows: int = 0, screen_dims: int = 0, graph: bool = False, index_all: bool = False,
+                 local_parts: int = 0, remscore: bool = False) -> Opts:
     o = Opts()
     load().apss_default_opts(ctypes.byref(o))
     o.stream = stream
@@ -213,6 +215,9 @@ def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, varia
     o.range_rows = range_rows
     o.screen_dims = screen_dims
     o.graph = 1 if graph else 0
+    o.index_all = 1 if index_all else 0
+    o.local_parts = local_parts
+    o.remscore = 1 if remscore else 0
     return o
 
 
@@ -347,7 +352,8 @@ class Index:
     @classmethod
     def build(cls, V, t_build: float, stream=None, query_safe: bool = True, head_dims: int = 0,
               on_device: bool = False, variant: int = -1, range_rows: int = 0, screen_dims: int = 0,
-              graph: bool = False) -> "Index":
+              graph: bool = False, index_all: bool = False, local_parts: int = 0,
+              remscore: bool = False) -> "Index":
         """V: object with n, m, row_ptr, col, val (numpy), or a tuple (n, m, row_ptr, col, val) of tensors."""
         if isinstance(V, tuple):
             n, m, rp, col, val = V
@@ -361,7 +367,8 @@ class Index:
         if stream is None:
             stream = current_stream_handle()
         h = build_index(n, m, rp, col, val, t_build, default_opts(stream, query_safe, head_dims, variant, range_rows,
-                                                                      screen_dims, graph))
+                                                                      screen_dims, graph, index_all, local_parts,
+                                                                      remscore))
         return cls(h, int(n), int(m))
 
     def join(self, t: float):

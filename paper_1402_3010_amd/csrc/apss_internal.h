@@ -93,6 +93,12 @@ hipError_t radix_sort_u64_u32(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, ui
 constexpr int64_t kSortSegment = 8192;
 hipError_t segment_sort_u64_u32(uint64_t* keys, uint32_t* vals, const int64_t* seg, int64_t nseg, hipStream_t s);
 
+// Keep the first of each run of equal keys of a sorted (key, value) array,
+// in place: the distinct pairs end in keys/vals[0, *total_dev).  flags holds
+// n int64, scan_tmp scan_tmp_elems(n), ktmp/vtmp n entries.
+hipError_t unique_sorted_u64_u32(uint64_t* keys, uint32_t* vals, int64_t n, int64_t* flags, int64_t* scan_tmp,
+                                 int64_t* total_dev, uint64_t* ktmp, uint32_t* vtmp, hipStream_t s);
+
 // Fill helpers (graph-safe kernels rather than memset nodes).
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);

@@ -259,8 +259,12 @@ int build_lists(apss_index* ix) {
   CHK(nidx.alloc(n + 1), "alloc");
   CHK(scan_tmp.alloc(scan_tmp_elems(n + 1)), "alloc");
   CHK(total.alloc(1), "alloc");
-  CHK(launch_cutoff(ix->rows.rp.p, ix->rows.rc.p, ix->mw_r.p, n, ix->t_build, ix->opts.query_safe ? 1 : 0,
-                    ix->head_cut, ix->rs.p, ix->rows.mw.p, nidx.p, s),
+  // head >= 0: the unindexed part of every row is its components of rank
+  // below head (the screened join's head cut, or nothing at all for the
+  // all-pairs-0-array index); -1: the paper's cutoff
+  const int32_t head = ix->opts.index_all ? 0 : (ix->head_cut > 0 ? ix->head_cut : -1);
+  CHK(launch_cutoff(ix->rows.rp.p, ix->rows.rc.p, ix->mw_r.p, n, ix->t_build, ix->opts.query_safe ? 1 : 0, head,
+                    ix->rs.p, ix->rows.mw.p, nidx.p, s),
       "cutoff");
   CHK(exclusive_scan_i64(nidx.p, n, scan_tmp.p, total.p, s), "scan");
   int64_t P = 0;
@@ -298,6 +302,27 @@ int build_lists(apss_index* ix) {
   CHK(ix->post4.alloc(P + kPost4Pad), "alloc");
   CHK(fill_u32(ix->post4.p + P, 0u, kPost4Pad, s), "fill");
   CHK(launch_pack_post4(ix->post.p, P, ix->post4.p, s), "post4");
+
+  // local pruning: split the indexed ranks into parts of about equal
+  // postings; ranks are in decreasing density, so the first parts hold the
+  // few heaviest lists and the last ones the long tail
+  ix->parts = ix->opts.local_parts > 1 ? ix->opts.local_parts : 1;
+  if (ix->parts > 1) {
+    std::vector<int64_t> off_h((size_t)m + 1);
+    CHK(hipMemcpyAsync(off_h.data(), ix->off.p, sizeof(int64_t) * (m + 1), hipMemcpyDeviceToHost, s), "read lists");
+    CHK(hipStreamSynchronize(s), "read lists");
+    ix->part_lo_host.assign((size_t)ix->parts + 1, 0);
+    for (int r = 1; r < ix->parts; ++r) {
+      const int64_t target = (P * r + ix->parts - 1) / ix->parts;
+      const int64_t k = std::lower_bound(off_h.begin(), off_h.end(), target) - off_h.begin();
+      ix->part_lo_host[(size_t)r] = (int32_t)std::max<int64_t>(ix->part_lo_host[(size_t)r - 1], std::min<int64_t>(k, m));
+    }
+    ix->part_lo_host[(size_t)ix->parts] = (int32_t)m;
+    CHK(ix->part_lo.alloc(ix->parts + 1), "alloc");
+    CHK(hipMemcpyAsync(ix->part_lo.p, ix->part_lo_host.data(), sizeof(int32_t) * (ix->parts + 1),
+                       hipMemcpyHostToDevice, s),
+        "parts");
+  }
 
   // per-block offsets of the dense lists, for the default tile variant
   int32_t H = ix->opts.head_dims > 0 ? ix->opts.head_dims : 32768;
@@ -414,7 +439,7 @@ int prepare(apss_index* ix, hipStream_t s, int variant, int64_t range_rows) {
     ix->toff_nR = nR;
     built = true;
   }
-  if (!ix->grid[variant]) ix->grid[variant] = join_resident_groups(variant);
+  if (!ix->grid[variant]) ix->grid[variant] = join_resident_groups(variant, ix->opts.remscore != 0);
   // other streams read the tables as soon as the lock is released
   if (built) CHK(hipStreamSynchronize(s), "prepare");
   return APSS_OK;
@@ -436,6 +461,7 @@ int plan_layout(apss_index* ix, const QuerySet& Q, int triangle, JoinLayout& L) 
   L.tiles = make_tiles(Q.rp_host, Q.n, L.QT, join_variant_staging(variant));
   L.ntiles = (int64_t)L.tiles.start.size() - 1;
   L.nrx = (L.nR + 7) / 8;
+  L.parts = ix->parts;
   L.cum.assign((size_t)(8 * (L.nrx + 1)), 0);
   for (int x = 0; x < 8; ++x) {
     int64_t c = 0;
@@ -448,7 +474,7 @@ int plan_layout(apss_index* ix, const QuerySet& Q, int triangle, JoinLayout& L) 
             triangle ? (int64_t)(std::upper_bound(L.tiles.start.begin() + 1, L.tiles.start.end(), R * range_rows) -
                                  (L.tiles.start.begin() + 1))
                      : 0;
-        c += L.ntiles - tmin;
+        c += (L.ntiles - tmin) * L.parts;
       }
     }
   }
@@ -492,6 +518,9 @@ void bind_plan(apss_index* ix, const QuerySet& Q, int triangle, float t, const f
   a.qctr = qctr_dev;
   a.wg_cur = wg_cur_dev;
   a.wg_cur_stride = L.wg_stride;
+  a.parts = L.parts;
+  a.part_lo = L.parts > 1 ? ix->part_lo.p : nullptr;
+  a.qadm = nullptr;
   P.variant = L.variant;
   P.G = L.G;
   P.bj = ceil_log2((uint64_t)ix->n);
@@ -587,6 +616,12 @@ int run_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, flo
   JoinPlan P;
   if ((rc = plan_join(ix, ws, Q, triangle, t, qt_dev, nullptr, P))) return rc;
   if ((rc = ensure_pair_capacity(ws, cap_hint))) return rc;
+  if (ix->opts.remscore) {
+    // each query's first component that admits new candidates (remscore)
+    CHK(ws.qadm.reserve(Q.n), "alloc");
+    CHK(launch_admit_pos(Q.rp, Q.rc, ix->mw_r.p, qt_dev, t, Q.n, ws.qadm.p, s), "admission");
+    P.a.qadm = ws.qadm.p;
+  }
   for (int attempt = 0; attempt < 2; ++attempt) {
     CHK(fill_u64((uint64_t*)ws.counters.p, 0ull, C_NUM, s), "fill");
     CHK(hipEventRecord(ws.ev[1], s), "event");
@@ -606,7 +641,22 @@ int run_join(apss_index* ix, Workspace& ws, const QuerySet& Q, int triangle, flo
     CHK(hipEventElapsedTime(&ms, ws.ev[1], ws.ev[2]), "event");
     ws.last.ms_candidates = ms;
     if ((rc = sort_pairs(ws, matches, P.bi + P.bj))) return rc;
-    *count = matches;
+    int64_t distinct = matches;
+    if (P.a.parts > 1 && matches > 1) {
+      // a pair kept by several parts was emitted once by each, with the same
+      // rescored similarity: keep one copy
+      SortScratch& ss = ws.ss;
+      CHK(ss.v64a.reserve(matches), "alloc");
+      CHK(ss.v64b.reserve(scan_tmp_elems(matches)), "alloc");
+      CHK(ws.uniq_total.reserve(1), "alloc");
+      CHK(unique_sorted_u64_u32(ws.raw_key.p, (uint32_t*)ws.raw_sim.p, matches, (int64_t*)ss.v64a.p,
+                                (int64_t*)ss.v64b.p, ws.uniq_total.p, ss.k2.p, ss.v32b.p, s),
+          "unique pairs");
+      CHK(hipMemcpyAsync(&distinct, ws.uniq_total.p, sizeof(int64_t), hipMemcpyDeviceToHost, s), "unique pairs");
+      CHK(hipStreamSynchronize(s), "unique pairs");
+      ws.last.matches = distinct;
+    }
+    *count = distinct;
     return APSS_OK;
   }
   set_error("pair buffer kept overflowing");
@@ -1119,6 +1169,18 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
     set_error("screen_dims must be in [0, %d]", kScreenMaxHead);
     return APSS_EINVAL;
   }
+  if (o.index_all < 0 || o.index_all > 1 || o.remscore < 0 || o.remscore > 1) {
+    set_error("index_all and remscore must be 0 or 1");
+    return APSS_EINVAL;
+  }
+  if (!(o.local_parts == 0 || o.local_parts == 1 || o.local_parts == 2 || o.local_parts == 4 || o.local_parts == 8)) {
+    set_error("local_parts must be 0, 1, 2, 4 or 8");
+    return APSS_EINVAL;
+  }
+  if (o.screen_dims > 0 && (o.index_all || o.local_parts > 1 || o.remscore)) {
+    set_error("screen_dims does not combine with index_all, local_parts or remscore");
+    return APSS_EINVAL;
+  }
   apss_index* ix = new (std::nothrow) apss_index();
   if (!ix) {
     set_error("host allocation failed");
@@ -1179,7 +1241,8 @@ int apss_join_device(apss_index* ix, float t, uint32_t* out_i, uint32_t* out_j, 
   }
   int rc = check_t(ix, t);
   if (rc) return rc;
-  if (ix->opts.graph && !ix->screen && ix->n > 0) return graph_join(ix, t, out_i, out_j, out_sim, capacity, count);
+  if (ix->opts.graph && !ix->screen && ix->parts == 1 && !ix->opts.remscore && ix->n > 0)
+    return graph_join(ix, t, out_i, out_j, out_sim, capacity, count);
   int64_t cnt = 0;
   if ((rc = self_join(ix, t, &cnt))) return rc;
   return finish_device(ix->ws, cnt, ceil_log2((uint64_t)ix->n), out_i, out_j, out_sim, capacity, count);

@@ -27,7 +27,8 @@ hipError_t launch_row_keys(const int64_t* rp, const int32_t* col, const float* v
                            int rbits, uint64_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_unpack_rows(const uint64_t* keys, const uint32_t* vals, int64_t nnz, int rbits, RComp* rc,
                               uint32_t* err, hipStream_t s);
-// head > 0: the unindexed part of every row is its components of rank < head (t and l2 unused)
+// head >= 0: the unindexed part of every row is its components of rank < head (t and l2 unused;
+// head = 0 indexes every component); head < 0: the running-bound cutoff at t
 hipError_t launch_cutoff(const int64_t* rp, const RComp* rc, const float* mw_r, int64_t n, float t, int l2,
                          int32_t head, RowStat* rs, float* xmw, int64_t* nidx, hipStream_t s);
 hipError_t launch_emit_indexed(const int64_t* rp, const RComp* rc, const RowStat* rs, const int64_t* ibase, int64_t n,

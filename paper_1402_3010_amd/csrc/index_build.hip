@@ -129,8 +129,10 @@ __global__ void k_cutoff(const int64_t* __restrict__ rp, const RComp* __restrict
       const RComp c = rc[a + k];
       const double w = (double)c.w;
       bool stop;
-      if (head > 0) {
-        stop = c.r >= head;  // head cut: the unindexed part is the head
+      if (head >= 0) {
+        // head cut: the unindexed part is the head (with head = 0 it is
+        // empty and every component is indexed)
+        stop = c.r >= head;
         sq += w * w;
       } else {
         b += w * (double)mw_r[c.r];

@@ -44,6 +44,16 @@ struct JoinArgs {
   unsigned int* qctr;     // [8] next item of each queue (zero at launch)
   uint32_t* wg_cur;       // per-workgroup cursors of tiles too large to stage in LDS
   int64_t wg_cur_stride;  // 2 * largest tile's component count
+  // local pruning (Lemma 1): parts > 1 splits every (range, tile) item into
+  // parts items, item part r scoring the indexed ranks [part_lo[r],
+  // part_lo[r + 1]) against the local threshold; survivors are decided on
+  // their exact full score, so a pair can be emitted by several parts
+  int32_t parts;          // 1: off
+  const int32_t* part_lo; // [parts + 1] rank bounds (device), or NULL when parts == 1
+  // remscore: qadm[q] = position of query q's first component that admits
+  // new candidates (components before it, the densest ones, only add to
+  // candidates admitted by a later one); NULL: off
+  const int32_t* qadm;
   // output
   uint64_t* out_key;      // [cap] (i << bj) | j
   float* out_sim;         // [cap]
@@ -64,8 +74,13 @@ int join_variant_geometry(int variant, int* queries_per_tile, int* block_rows);
 // Components of one tile that the variant stages in LDS.
 int join_variant_staging(int variant);
 hipError_t launch_join(const JoinArgs& a, int variant, int grid, hipStream_t s);
-// Workgroups of a variant that fit on the device at once.
-int join_resident_groups(int variant);
+// Workgroups of a variant (with or without the remscore rule) that fit on the device at once.
+int join_resident_groups(int variant, bool remscore = false);
+// qadm[q] = position of the first component of query row q (rank space,
+// densest first) at which sum_{i <= k} q_i * maxweight_{r_i}(V) reaches its
+// threshold (qt[q], or t when qt is NULL); the row length if it never does.
+hipError_t launch_admit_pos(const int64_t* qrp, const RComp* qrc, const float* mw_r, const float* qt, float t,
+                            int64_t nq, int32_t* qadm, hipStream_t s);
 hipError_t launch_range_offsets(const int64_t* off, const Post* post, int32_t H, int64_t m, int64_t nR,
                                 int64_t range_rows, uint32_t* toff, hipStream_t s);
 hipError_t launch_max_tile_nnz(const int64_t* qrp, int64_t nq, int qt, unsigned long long* out, hipStream_t s);

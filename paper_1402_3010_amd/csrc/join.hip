@@ -116,7 +116,7 @@ struct Cfg {
   static constexpr int WPE = WPE_;  // waves per SIMD the register budget must allow
 };
 
-template <class C>
+template <class C, bool REM>
 struct Smem {
   // the per-tile fields first: at small offsets, so that reads of them at
   // fixed addresses share one base register (the address offset a
@@ -138,6 +138,9 @@ struct Smem {
   int64_t item;
   unsigned long long cnt[C_NUM];
   uint32_t acc[C::QT * C::CB];
+  // remscore: admission bits, of row y - block start (bit = query slot) on
+  // the block path and of hash slot h (word h / 32) on the hashed path
+  uint32_t adm[REM ? C::CB : 1];
   float qd[C::QT * C::RD];
   Seg seg[C::QB];
   int32_t segpre[C::QB + 1];
@@ -158,7 +161,7 @@ struct Smem {
   uint16_t first_sink[64];
   RComp qrow[C::QB];     // staged components of the tile
   uint2 cur[C::QB];      // list cursor of each staged component: {position, vector id at it}
-  uint8_t cqi[C::QB];    // query slot of each staged component
+  uint8_t cqi[C::QB];    // query slot of each staged component; bit 7: it admits new candidates (remscore)
 };
 
 // Orders the LDS accesses of one wave around an exchange between its lanes
@@ -176,9 +179,12 @@ __device__ __forceinline__ float min_nonneg(float x, float y) {
   return __uint_as_float(min(__float_as_uint(x), __float_as_uint(y)));
 }
 
-template <class C>
+// REM: the remscore rule -- a candidate counts only once a component that
+// admits new candidates has reached it (admission bits beside the scores).
+template <class C, bool REM>
 __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE))) void k_join(JoinArgs a) {
-  constexpr int QT = C::QT, CB = C::CB, NT = C::NT, RD = C::RD, SQ = Smem<C>::SQE, QB = C::QB, U = C::U, UL = C::UL;
+  constexpr int QT = C::QT, CB = C::CB, NT = C::NT, RD = C::RD, SQ = Smem<C, REM>::SQE, QB = C::QB, U = C::U,
+                UL = C::UL;
   constexpr int NW = NT / 64;
   constexpr int KMAX = QB / NT;  // staged components per thread
   constexpr int YPT = CB / NT;   // corpus rows per thread in the filter
@@ -189,7 +195,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   // 3/4 of the table size) and its per-batch tags fit a byte
   static_assert((QT * CB / 2) * 3 / 4 / 64 + 1 <= QB * (kLongSeg - 1) / 64 + 2, "chunk table");
   static_assert((QB * (kLongSeg - 1) / NW + 64) / (64 * U) + 2 < 255, "stream tags");
-  __shared__ Smem<C> sm;
+  __shared__ Smem<C, REM> sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = uni(tid >> 6);
@@ -200,6 +206,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   const __amdgpu_buffer_rsrc_t prs = make_rsrc(a.post4, a.post4_bytes);
   // the accumulators start at zero and every item leaves them at zero
   for (int e = tid; e < QT * CB; e += NT) sm.acc[e] = 0u;
+  if constexpr (REM)
+    for (int e = tid; e < CB; e += NT) sm.adm[e] = 0u;
 
   // Persistent loop over work items (corpus range R, query tile T).  The
   // queue of XCD x holds the ranges R = x, x + 8, ... in order, so the
@@ -235,7 +243,16 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       __syncthreads();
       const int lo_j = uni(sm.slot);
       const int64_t R = (int64_t)x + 8 * (int64_t)lo_j;
-      const int64_t tile = a.ntiles - 1 - (it - cum[lo_j]);
+      int64_t u = it - cum[lo_j];
+      // local pruning: consecutive items of a (range, tile) score its parts
+      int32_t plo = 0, phi = 0x7FFFFFFF;
+      if (a.parts > 1) {
+        const int64_t pr = u % a.parts;
+        u /= a.parts;
+        plo = a.part_lo[pr];
+        phi = a.part_lo[pr + 1];
+      }
+      const int64_t tile = a.ntiles - 1 - u;
       const int64_t b_begin = R * a.K;
   const int64_t q0 = a.tstart[tile];
   const int qn = (int)(a.tstart[tile + 1] - q0);
@@ -281,8 +298,13 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     // scaling by a power of two commutes with float rounding, so comparing
     // the raw accumulator with them decides exactly as in score units.
     const int ql = tid < qn ? (int)(sm.qoff[tid + 1] - sm.qoff[tid]) : 0;
-    sm.qb[tid] = make_float4((sm.qt[tid] - kSlack) * kFix, sm.qmw[tid] * kFix, (float)ql * sm.qmw[tid] * kFix,
-                             sm.qpn[tid] * kFix);
+    // With local pruning over p parts (a power of two) every bound is
+    // divided by p: the size test is unchanged, and the score tests become
+    // A_r + U/p >= (t - slack)/p, the local test of Lemma 1 with the bound U
+    // of the unindexed part shared evenly by the parts.
+    const float fx = a.parts > 1 ? kFix / (float)a.parts : kFix;
+    sm.qb[tid] = make_float4((sm.qt[tid] - kSlack) * fx, sm.qmw[tid] * fx, (float)ql * sm.qmw[tid] * fx,
+                             sm.qpn[tid] * fx);
   }
   // query slot of tile component k: the last qi with qoff[qi] <= k
   auto find_slot = [&](int64_t k) {
@@ -308,6 +330,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     for (int64_t k = tid; k < tile_nnz; k += NT) {
       const RComp c = a.qrc[qbase + k];
       const int qi = find_slot(qbase + k);
+      bool admits = true;  // remscore: the component admits new candidates
+      if constexpr (REM) admits = qbase + k - sm.qoff[qi] >= (int64_t)a.qadm[q0 + qi];
       if (c.r < RD) sm.qd[qi * RD + c.r] = c.w;
       uint32_t p0, p1, ny = 0;
       if (c.r < a.H) {
@@ -320,18 +344,21 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         // staged tiles it is loaded once the item is known to take that path
         if (!staged) ny = (int64_t)p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
       }
-      const bool dead = p1 == p0;  // no list entry in the item's corpus range
+      // no list entry in the item's corpus range, or a rank outside the item's part
+      const bool dead = p1 == p0 || c.r < plo || c.r >= phi;
+      if (dead) p1 = p0;
       vmine += (int32_t)(p1 - p0);
       if (staged) {
         sm.qrow[k] = c;
-        sm.cqi[k] = (uint8_t)qi;
+        sm.cqi[k] = (uint8_t)(qi | (admits ? 0x80 : 0));
         // the component's entries in the whole range, for a hashed item
         // (whose segments are all short enough for the 16-bit length)
         if (!dead) {
           Seg sg;
           sg.pos = p0;
           sg.lenq = ((p1 - p0) & 0xFFFFu) | ((uint32_t)qi << 16);
-          sg.q = q15(c.w);
+          // bit 31 (remscore): the component admits; the 24-bit product ignores it
+          sg.q = q15(c.w) | (REM && admits ? 0x80000000u : 0u);
           sm.seg[QB - 1 - atomicAdd(&sm.nshort, 1)] = sg;
         }
         sm.cur[k] = make_uint2(dead ? kDead : p0, ny);
@@ -341,7 +368,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             if (k == (int64_t)j * NT + tid) hn[j] = a.hoff[(b_begin + 1) * (int64_t)a.H + c.r];
         }
       } else {
-        gcur[2 * k] = p0;
+        gcur[2 * k] = dead ? kDead : p0;
         gcur[2 * k + 1] = ny;
       }
     }
@@ -477,8 +504,12 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     const int ns = uni(sm.qcount < SQ ? sm.qcount : SQ);
     // verify s = A + dot(q, y'); y' is the first cut components of the row,
     // densest dimension first.  Few survivors: one wave per survivor, lanes
-    // over y' (short latency chain); many: one lane per survivor.
-    if (ns <= 4 * NW) {
+    // over y' (short latency chain); many: one lane per survivor.  With
+    // local pruning A is one part's score only: every survivor goes to the
+    // rescore, which decides on the full dot product.
+    if (a.parts > 1) {
+      if (tid == 0) c_ver += (unsigned long long)ns;
+    } else if (ns <= 4 * NW) {
       for (int e = wave; e < ns; e += NW) {
         const uint4 it = sm.sq[e];
         const int qi = (int)(it.x >> 16);
@@ -588,6 +619,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         const uint32_t old = atomicCAS(&hkey[h], 0u, key);
         if (old == 0u || old == key) {
           atomicAdd(&hval[h], packed_product(qw, p));
+          if constexpr (REM)
+            if (qw >> 31) atomicOr(&sm.adm[h >> 5], 1u << (h & 31u));
           break;
         }
         h = (h + 1u) & (uint32_t)(HS - 1);
@@ -619,6 +652,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             const int qi = (int)((kk[g] - 1u) >> 16);
             yv[g] = rbeg + (int64_t)((kk[g] - 1u) & 0xFFFFu);
             ok[g] = kk[g] != 0u && yv[g] < a.n && !(a.triangle && yv[g] >= q0 + qi);
+            if constexpr (REM) ok[g] = ok[g] && ((sm.adm[h >> 5] >> (h & 31)) & 1u);
             stg[g] = a.rs[ok[g] ? yv[g] : 0];
           }
 #pragma unroll
@@ -660,6 +694,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             if (kk[g] && !retry) {
               hkey[h] = 0u;
               hval[h] = 0u;
+              if constexpr (REM) atomicAnd(&sm.adm[h >> 5], ~(1u << (h & 31)));
             }
           }
         }
@@ -676,7 +711,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             yl = (int)((kk - 1u) & 0xFFFFu);
             const int64_t y = rbeg + yl;
             av = hval[h];
-            if (y < a.n && !(a.triangle && y >= q0 + qi)) {
+            bool adm_ok = true;
+            if constexpr (REM) adm_ok = (sm.adm[h >> 5] >> (h & 31)) & 1u;
+            if (adm_ok && y < a.n && !(a.triangle && y >= q0 + qi)) {
               const RowStat st = a.rs[y];
               const int ylen = st.len;
               packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
@@ -708,6 +745,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           if (kk && !retry) {
             hkey[h] = 0u;
             hval[h] = 0u;
+            if constexpr (REM) atomicAnd(&sm.adm[h >> 5], ~(1u << (h & 31)));
           }
         }
       }
@@ -765,6 +803,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       uint32_t tpos[KMAX], tend[KMAX];
       float tw[KMAX];
       int tqi[KMAX];
+      bool tadm[KMAX];  // remscore: the sparse list's component admits new candidates
       // (one copy of the loop per tile kind; the staged one has no
       // conditional loads, whose results later code would wait for)
       auto pass1 = [&](auto kind) {
@@ -781,7 +820,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             // in bounds, and a component that is not a sparse hit loads the
             // lists' first entry instead of its own
             const RComp c = sm.qrow[k];
-            const int qi = sm.cqi[k];
+            const int cq8 = sm.cqi[k];
+            const int qi = cq8 & 0x7F;
+            const bool admits = REM && (cq8 >> 7);
             const uint2 cu = sm.cur[k];
             const uint32_t pos = cu.x, ny = cu.y;
             const bool live = k < tile_nnz && pos != kDead;
@@ -791,13 +832,14 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             has_seg = live && dense && e > pos;
             sg.pos = pos;
             sg.lenq = (e - pos) | ((uint32_t)qi << 16);
-            sg.q = q15(c.w);
+            sg.q = q15(c.w) | (admits ? 0x80000000u : 0u);
             if (has_seg) sm.cur[k] = make_uint2(e, 0u);
             const bool hit = live && !dense && (int64_t)ny < blk1;
             thit[j] = hit;
             tpos[j] = pos;
             tw[j] = c.w;
             tqi[j] = qi;
+            tadm[j] = admits;
             const uint32_t pp = hit ? pos : 0u;
             tend[j] = (uint32_t)a.off[hit ? c.r + 1 : 0];
             t0[j] = a.post[pp];
@@ -805,6 +847,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           } else if (k < tile_nnz) {
             const RComp c = a.qrc[qbase + k];
             const int qi = find_slot(qbase + k);
+            bool admits = false;
+            if constexpr (REM) admits = qbase + k - sm.qoff[qi] >= (int64_t)a.qadm[q0 + qi];
             const uint32_t pos = gcur[2 * k], ny = gcur[2 * k + 1];
             if (pos == kDead) {
               // no entry of this list in the item's range
@@ -814,7 +858,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
                 has_seg = true;
                 sg.pos = pos;
                 sg.lenq = (e - pos) | ((uint32_t)qi << 16);
-                sg.q = q15(c.w);
+                sg.q = q15(c.w) | (admits ? 0x80000000u : 0u);
                 gcur[2 * k] = e;
               }
             } else if ((int64_t)ny < blk1) {
@@ -822,6 +866,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
               tpos[j] = pos;
               tw[j] = c.w;
               tqi[j] = qi;
+              tadm[j] = admits;
               tend[j] = (uint32_t)a.off[c.r + 1];
               t0[j] = a.post[pos];
               t1y[j] = a.post[pos + 1].y;
@@ -918,12 +963,16 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           const uint32_t end = tend[j];
           const int ab = tqi[j] * CB - (int)blk0;
           atomicAdd(&sm.acc[ab + (int)t0[j].y], fixp(tw[j], t0[j].w));
+          if constexpr (REM)
+            if (tadm[j]) atomicOr(&sm.adm[(int)t0[j].y - (int)blk0], 1u << tqi[j]);
           ++c_tail;
           ++pos;
           uint32_t ny = pos < end ? t1y[j] : 0xFFFFFFFFu;
           while ((int64_t)ny < blk1) {
             const Post p = a.post[pos];
             atomicAdd(&sm.acc[ab + (int)p.y], fixp(tw[j], p.w));
+            if constexpr (REM)
+              if (tadm[j]) atomicOr(&sm.adm[(int)p.y - (int)blk0], 1u << tqi[j]);
             ++c_tail;
             ++pos;
             ny = pos < end ? a.post[pos].y : 0xFFFFFFFFu;
@@ -941,6 +990,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw, bool live) {
         // a lane past the slice adds zero to a slot of its row (no branch)
         atomicAdd(&sm.acc[qi * CB + (int)(p & (CB - 1))], live ? packed_product(qw, p) : 0u);
+        if constexpr (REM)
+          if (live && (qw >> 31)) atomicOr(&sm.adm[p & (CB - 1)], 1u << qi);
       });
       // long segments: wave w takes segments w, w + NW, ... in chunks of 64
       // entries (one per lane).  Lane i holds the descriptor of the wave's
@@ -1004,6 +1055,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           for (int u = 0; u < UL; ++u) {
             const uint32_t w = lane < ccnt[u] ? packed_product(cq[u], p[u]) : 0u;
             atomicAdd(&sm.acc[and_or(p[u], (uint32_t)(CB - 1), cab[u])], w);
+            if constexpr (REM)
+              if ((cq[u] >> 31) && lane < ccnt[u]) atomicOr(&sm.adm[p[u] & (CB - 1)], 1u << (cab[u] / CB));
           }
         };
         uint32_t aoff[UL], aq[UL], pa[UL], boff[UL], bq[UL], pb[UL], aab[UL], bab[UL];
@@ -1059,13 +1112,16 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         uint32_t av[QT];
 #pragma unroll
         for (int qi = 0; qi < QT; ++qi) av[qi] = sm.acc[qi * CB + yl];
+        uint32_t abits = ~0u;  // remscore: slots whose candidate was admitted
+        if constexpr (REM) abits = sm.adm[yl];
         // the bounds of all slots first, without branches; the rare
         // survivors are then queued slot by slot
         uint32_t wbits = 0u, ncand = 0u;
 #pragma unroll
         for (int qi = 0; qi < QT; ++qi) {
           const float4 qb = sm.qb[qi];
-          const bool live = FULL ? (av[qi] != 0u) : ((av[qi] != 0u) & (qi >= qlo));
+          bool live = FULL ? (av[qi] != 0u) : ((av[qi] != 0u) & (qi >= qlo));
+          if constexpr (REM) live = live & (((abits >> qi) & 1u) != 0u);
           const float A = (float)av[qi];  // accumulator units, as the bounds
           const bool want = live & (ylf * qb.y >= qb.x) & (A + min_nonneg(cutf * qb.y, qb.z) * st.pmw >= qb.x) &
                             (A + qb.w * st.pnrm >= qb.x);
@@ -1098,6 +1154,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         }
 #pragma unroll
         for (int qi = 0; qi < QT; ++qi) sm.acc[qi * CB + yl] = ((keep >> qi) & 1u) ? av[qi] : 0u;
+        if constexpr (REM) sm.adm[yl] = abits & keep;
         c_cand += ncand;
       }
     };
@@ -1147,6 +1204,34 @@ __global__ void k_range_offsets(const int64_t* __restrict__ off, const Post* __r
       else hi = mid;
     }
     toff[e] = (uint32_t)lo;
+  }
+}
+
+// Remscore (all-pairs-2, Section 3.2.2): a query's components are processed
+// rarest first and admit new candidates while the remaining bound -- the sum
+// of q_i * maxweight_i(V) over the components not yet processed, the current
+// one included -- is at least t.  In rank space (densest first) that bound
+// is the prefix sum up to the component, so the admitting components are
+// those from the first position where the prefix sum reaches t onward.  The
+// sum is taken in double over exact float products; the comparison is made
+// against t less 1e-9, which only admits earlier.
+__global__ void k_admit_pos(const int64_t* __restrict__ qrp, const RComp* __restrict__ qrc,
+                            const float* __restrict__ mw_r, const float* __restrict__ qt, float t, int64_t nq,
+                            int32_t* __restrict__ qadm) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a0 = qrp[q], a1 = qrp[q + 1];
+    const double tq = (double)(qt ? qt[q] : t) - 1e-9;
+    double b = 0.0;
+    int32_t pos = (int32_t)(a1 - a0);
+    for (int64_t k = a0; k < a1; ++k) {
+      const RComp c = qrc[k];
+      b += (double)c.w * (double)mw_r[c.r];
+      if (b >= tq) {
+        pos = (int32_t)(k - a0);
+        break;
+      }
+    }
+    qadm[q] = pos;
   }
 }
 
@@ -1217,7 +1302,10 @@ int join_variant_geometry(int v, int* qt, int* cb) {
 
 template <class C>
 hipError_t launch_variant(const JoinArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_join<C>), dim3((unsigned)grid), dim3(C::NT), 0, s, a);
+  if (a.qadm)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_join<C, true>), dim3((unsigned)grid), dim3(C::NT), 0, s, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_join<C, false>), dim3((unsigned)grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1235,24 +1323,22 @@ hipError_t launch_join(const JoinArgs& a, int variant, int grid, hipStream_t s) 
 }
 
 template <class C>
-int resident(int cus) {
+int resident(int cus, bool rem) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_join<C>), C::NT, 0) !=
-          hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
+  const void* f = rem ? reinterpret_cast<const void*>(&k_join<C, true>) : reinterpret_cast<const void*>(&k_join<C, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, C::NT, 0) != hipSuccess || per_cu < 1) per_cu = 1;
   return per_cu * cus;
 }
 
-int join_resident_groups(int variant) {
+int join_resident_groups(int variant, bool remscore) {
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
   switch (variant) {
-    case 0: return resident<V0>(cus);
-    case 1: return resident<V1>(cus);
-    case 2: return resident<V2>(cus);
-    case 3: return resident<V3>(cus);
+    case 0: return resident<V0>(cus, remscore);
+    case 1: return resident<V1>(cus, remscore);
+    case 2: return resident<V2>(cus, remscore);
+    case 3: return resident<V3>(cus, remscore);
     default: return cus;
   }
 }
@@ -1262,6 +1348,13 @@ hipError_t launch_range_offsets(const int64_t* off, const Post* post, int32_t H,
   const int64_t total = (nR + 1) * (m - H);
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_range_offsets, dim3(grid(total)), dim3(256), 0, s, off, post, H, m, nR, range_rows, toff);
+  return hipGetLastError();
+}
+
+hipError_t launch_admit_pos(const int64_t* qrp, const RComp* qrc, const float* mw_r, const float* qt, float t,
+                            int64_t nq, int32_t* qadm, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_admit_pos, dim3(grid(nq)), dim3(256), 0, s, qrp, qrc, mw_r, qt, t, nq, qadm);
   return hipGetLastError();
 }
 

@@ -124,6 +124,8 @@ struct Workspace {
   DBuf<unsigned int> qctr;
   DBuf<uint32_t> wg_cur;
   DBuf<unsigned long long> counters;
+  DBuf<int64_t> uniq_total;  // distinct pairs after a join with local pruning
+  DBuf<int32_t> qadm;        // remscore: first admitting component of each query
   DBuf<uint64_t> raw_key;
   DBuf<float> raw_sim;
   DBuf<float> qt;
@@ -149,7 +151,7 @@ struct Workspace {
   }
   int64_t bytes() const {
     return ss.bytes() + tstart.bytes() + qcum.bytes() + qctr.bytes() + wg_cur.bytes() + counters.bytes() +
-           raw_key.bytes() + raw_sim.bytes() + qt.bytes() + q_col.bytes() + q_val.bytes() + s_keys.bytes() + s_cand.bytes() + s_sid.bytes() +
+           raw_key.bytes() + raw_sim.bytes() + qt.bytes() + uniq_total.bytes() + qadm.bytes() + q_col.bytes() + q_val.bytes() + s_keys.bytes() + s_cand.bytes() + s_sid.bytes() +
            s_tiles.bytes() + s_nh.bytes() + s_X.bytes();
   }
 };
@@ -173,6 +175,10 @@ struct apss_index {
   apss::DBuf<int64_t> off;
   apss::DBuf<apss::Post> post;
   apss::DBuf<uint32_t> post4;  // packed copy of post for streaming
+  // local pruning: rank bounds of the parts (parts + 1 entries)
+  int32_t parts = 1;
+  apss::DBuf<int32_t> part_lo;
+  std::vector<int32_t> part_lo_host;
   // lazily built tables (guarded by prep_mu)
   std::mutex prep_mu;
   apss::DBuf<uint32_t> hoff[2];  // per-block offsets of the dense lists (block width 1024, 2048)
@@ -203,7 +209,7 @@ struct Tiles {
 // Host side of one join kernel launch: geometry, query tiles and the
 // cumulative item counts of the 8 per-XCD work queues.
 struct JoinLayout {
-  int variant = 0, QT = 0, CB = 0, slot = 0, K = 0, G = 0;
+  int variant = 0, QT = 0, CB = 0, slot = 0, K = 0, G = 0, parts = 1;
   int64_t nb = 0, nR = 0, nrx = 0, ntiles = 0, wg_stride = 0;
   Tiles tiles;
   std::vector<int64_t> cum;  // 8 * (nrx + 1)

@@ -90,8 +90,8 @@ extern "C" int apss_join_device_noalloc(apss_index* ix, float t, uint32_t* out_i
   *count = 0;
   int rc = check_t(ix, t);
   if (rc) return rc;
-  if (ix->screen) {
-    set_error("the allocation-free join serves indexes built without screen_dims");
+  if (ix->screen || ix->parts > 1 || ix->opts.remscore) {
+    set_error("the allocation-free join serves indexes built without screen_dims, local_parts or remscore");
     return APSS_EINVAL;
   }
   int dev = -1;

@@ -338,6 +338,40 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+
+// 1 where a sorted key differs from its predecessor
+__global__ void k_unique_flags(const uint64_t* __restrict__ keys, int64_t n, int64_t* __restrict__ flags) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    flags[k] = (k == 0 || keys[k] != keys[k - 1]) ? 1 : 0;
+}
+
+// first copy of each key (and its value) to its rank among the distinct keys
+__global__ void k_unique_scatter(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                 const int64_t* __restrict__ pos, int64_t n, uint64_t* __restrict__ okeys,
+                                 uint32_t* __restrict__ ovals) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    if (k == 0 || keys[k] != keys[k - 1]) {
+      okeys[pos[k]] = keys[k];
+      ovals[pos[k]] = vals[k];
+    }
+}
+
+}  // namespace
+
+hipError_t unique_sorted_u64_u32(uint64_t* keys, uint32_t* vals, int64_t n, int64_t* flags, int64_t* scan_tmp,
+                                 int64_t* total_dev, uint64_t* ktmp, uint32_t* vtmp, hipStream_t s) {
+  if (n <= 0) return exclusive_scan_i64(flags, 0, scan_tmp, total_dev, s);
+  hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, n, flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = exclusive_scan_i64(flags, n, scan_tmp, total_dev, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unique_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, vals, flags, n, ktmp, vtmp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(keys, ktmp, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  return hipMemcpyAsync(vals, vtmp, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+}
+
 hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (!p) return hipErrorInvalidValue;

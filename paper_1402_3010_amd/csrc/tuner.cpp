@@ -49,6 +49,13 @@ std::string tune_key(const apss_index* ix, float t) {
     const size_t l = strlen(buf);
     snprintf(buf + l, sizeof(buf) - l, "|head=%d", ix->screen->head_cut);
   }
+  // the variants of the algorithm are tuned apart from the default join
+  if (ix->opts.index_all) strncat(buf, "|index_all", sizeof(buf) - strlen(buf) - 1);
+  if (ix->opts.local_parts > 1) {
+    const size_t l = strlen(buf);
+    snprintf(buf + l, sizeof(buf) - l, "|local=%d", ix->opts.local_parts);
+  }
+  if (ix->opts.remscore) strncat(buf, "|remscore", sizeof(buf) - strlen(buf) - 1);
   return buf;
 }
 

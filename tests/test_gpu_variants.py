@@ -1,0 +1,193 @@
+"""GPU parity of the algorithm variants beside the default join:
+
+* all-pairs-0-array (index_all): every component indexed, dense score
+  arrays per corpus block (Section 4) -- the ablation of partial indexing;
+* local pruning (local_parts = p): the indexed dimensions split into p rank
+  ranges scored by separate work items against the local threshold t/p
+  (Section 5.1.3, Eq. 1 and Lemma 1), survivors decided on their exact score;
+* remscore: new candidates admitted only while the remaining bound of the
+  query's unprocessed components reaches t (all-pairs-2, Section 3.2.2).
+
+Each must return the oracle's pair set (and, because every reported pair is
+decided by the same exact rescore, the default join's pairs bit for bit).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth.corpus import CorpusSpec, from_rows, make_corpus, spec_for
+from tests.parity import assert_parity
+from tests.test_oracle import load_golden
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apss():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.init()
+    import paper_1402_3010_amd as m
+    m.load()
+    return m
+
+
+def join(apss, V, t, **kw):
+    print("variant join n=%d t=%.2f %s" % (V.n, t, kw), flush=True)
+    ix = apss.Index.build(V, np.float32(t), **kw)
+    try:
+        i, j, s = ix.join(np.float32(t))
+        st = ix.stats()
+        cut = ix.export()[2]
+    finally:
+        ix.close()
+    return i, j, s, st, cut
+
+
+def assert_identical(a, b):
+    assert len(a[0]) == len(b[0]), (len(a[0]), len(b[0]))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2].view(np.uint32), b[2].view(np.uint32))
+
+
+CASES = [("c1", None, 0.5), ("c2", 21111, 0.5), ("c2", 21111, 0.7), ("c2", 21111, 0.9), ("c3", 20000, 0.7),
+         ("c4", 20000, 0.8)]
+
+
+@pytest.fixture(scope="module")
+def corpora():
+    return {(name, n): make_corpus(spec_for(name, n=n)) for name, n, _ in CASES}
+
+
+@pytest.fixture(scope="module")
+def default_joins(apss, corpora):
+    return {(name, n, t): join(apss, corpora[(name, n)], t) for name, n, t in CASES}
+
+
+# ---------------------------------------------------------------- all-pairs-0-array
+
+
+@pytest.mark.parametrize("name,n,t", CASES)
+def test_index_all(apss, corpora, default_joins, name, n, t):
+    V = corpora[(name, n)]
+    res = join(apss, V, t, index_all=True)
+    i, j, s, st, cut = res
+    assert (cut == 0).all()
+    ref = oracle.join_plain(V, np.float32(t))
+    assert_parity(i, j, s, ref, float(np.float32(t)), V)
+    # every pair sharing a dimension is a candidate: the oracle's count
+    assert st["candidates"] == ref.candidates
+    assert_identical(default_joins[(name, n, t)], res)
+
+
+def test_index_all_queries_and_golden(apss):
+    V = make_corpus(spec_for("c2", n=9000))
+    Q = make_corpus(CorpusSpec(400, V.m, "lognormal", 80, 1.0, 5, 2000, 1.1, 4343))
+    tq = np.random.default_rng(3).uniform(0.3, 0.9, size=Q.n).astype(np.float32)
+    ix = apss.Index.build(V, np.float32(0.3), index_all=True)
+    try:
+        i, j, s = ix.query(Q, t_per_row=tq)
+    finally:
+        ix.close()
+    assert_parity(i, j, s, oracle.query(V, Q, t_per_row=tq.astype(np.float64)), None, Q, V,
+                  per_row_t=tq.astype(np.float64))
+    G, rank, mw, cases = load_golden()
+    for c in cases:
+        gi, gj, gs, _, _ = join(apss, G, c["t"], index_all=True)
+        assert list(zip(gi.tolist(), gj.tolist())) == [(a, b) for a, b, _ in c["pairs"]]
+        assert list(gs) == [np.float32(x) for _, _, x in c["pairs"]]
+
+
+# ---------------------------------------------------------------- local pruning
+
+
+@pytest.mark.parametrize("parts", [2, 4, 8])
+@pytest.mark.parametrize("name,n,t", CASES)
+def test_local_pruning(apss, corpora, default_joins, name, n, t, parts):
+    V = corpora[(name, n)]
+    res = join(apss, V, t, local_parts=parts)
+    i, j, s, st, _ = res
+    assert_parity(i, j, s, oracle.join_plain(V, np.float32(t)), float(np.float32(t)), V)
+    assert_identical(default_joins[(name, n, t)], res)
+    assert st["matches"] == len(i)
+    # every part's local candidates together are at least the distinct candidates
+    assert st["candidates"] >= default_joins[(name, n, t)][3]["candidates"] // parts
+
+
+def test_local_pruning_queries_and_edges(apss):
+    V = make_corpus(spec_for("c2", n=9000))
+    Q = V.take_rows(np.arange(1, 9000, 37))
+    tq = np.random.default_rng(4).uniform(0.5, 0.95, size=Q.n).astype(np.float32)
+    for parts in (2, 8):
+        ix = apss.Index.build(V, np.float32(0.5), local_parts=parts)
+        try:
+            i, j, s = ix.query(Q, t_per_row=tq)
+        finally:
+            ix.close()
+        assert_parity(i, j, s, oracle.query(V, Q, t_per_row=tq.astype(np.float64)), None, Q, V,
+                      per_row_t=tq.astype(np.float64))
+    # identical vectors: every pair is reported once although every part keeps it
+    base = make_corpus(spec_for("c1", n=1))
+    row = dict(zip(base.row(0)[0].tolist(), base.row(0)[1].tolist()))
+    W = from_rows([row] * 700, base.m)
+    for parts in (2, 4):
+        i, j, s, st, _ = join(apss, W, 0.999, local_parts=parts)
+        assert len(i) == 700 * 699 // 2
+        assert np.all(np.diff(i.astype(np.int64) * 1000 + j) > 0)
+    G, rank, mw, cases = load_golden()
+    for c in cases:
+        gi, gj, gs, _, _ = join(apss, G, c["t"], local_parts=4)
+        assert list(zip(gi.tolist(), gj.tolist())) == [(a, b) for a, b, _ in c["pairs"]]
+        assert list(gs) == [np.float32(x) for _, _, x in c["pairs"]]
+    with pytest.raises(apss.ApssError) as e:
+        apss.Index.build(V, np.float32(0.5), local_parts=3)
+    assert e.value.code == apss.APSS_EINVAL
+
+
+# ---------------------------------------------------------------- remscore
+
+
+@pytest.mark.parametrize("name,n,t", CASES)
+def test_remscore(apss, corpora, default_joins, name, n, t):
+    V = corpora[(name, n)]
+    res = join(apss, V, t, remscore=True)
+    i, j, s, st, _ = res
+    tt = np.float32(t)
+    assert_parity(i, j, s, oracle.join_plain(V, tt), float(tt), V)
+    assert_identical(default_joins[(name, n, t)], res)
+    # the admitted candidates are the oracle's remscore candidates
+    pre = oracle.join_prefix(V, tt, oracle.FLAG_REMSCORE | oracle.FLAG_L2_CLAUSE)
+    assert st["candidates"] == pre.candidates
+    assert st["candidates"] < default_joins[(name, n, t)][3]["candidates"]
+
+
+def test_remscore_combinations_and_queries(apss):
+    V = make_corpus(spec_for("c2", n=12000))
+    t = np.float32(0.6)
+    ref = oracle.join_plain(V, t)
+    base = join(apss, V, t)
+    for kw in (dict(remscore=True, index_all=True), dict(remscore=True, local_parts=4),
+               dict(remscore=True, index_all=True, local_parts=2),
+               # every tile variant, and narrow ranges whose items take the hashed path
+               dict(remscore=True, variant=0), dict(remscore=True, variant=2), dict(remscore=True, range_rows=1024),
+               dict(remscore=True, variant=2, range_rows=2048, local_parts=2),
+               dict(local_parts=8, variant=0), dict(local_parts=2, range_rows=1024), dict(index_all=True, variant=2)):
+        res = join(apss, V, t, **kw)
+        assert_parity(res[0], res[1], res[2], ref, float(t), V)
+        assert_identical(base, res)
+    Q = V.take_rows(np.arange(0, 12000, 53))
+    tq = np.random.default_rng(5).uniform(0.5, 0.95, size=Q.n).astype(np.float32)
+    ix = apss.Index.build(V, np.float32(0.5), remscore=True)
+    try:
+        i, j, s = ix.query(Q, t_per_row=tq)
+    finally:
+        ix.close()
+    assert_parity(i, j, s, oracle.query(V, Q, t_per_row=tq.astype(np.float64)), None, Q, V,
+                  per_row_t=tq.astype(np.float64))
+    G, rank, mw, cases = load_golden()
+    for c in cases:
+        gi, gj, gs, _, _ = join(apss, G, c["t"], remscore=True)
+        assert list(zip(gi.tolist(), gj.tolist())) == [(a, b) for a, b, _ in c["pairs"]]
+    with pytest.raises(apss.ApssError) as e:
+        apss.Index.build(V, np.float32(0.5), remscore=True, screen_dims=64)
+    assert e.value.code == apss.APSS_EINVAL

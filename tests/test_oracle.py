@@ -222,7 +222,7 @@ def test_empty_rows_never_match():
 # ---------------------------------------------------------------- lossless pruning
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2, 3, 4, 7])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3, 4, 7, 8, 12, 15])
 def test_prefix_equals_plain(flags):
     V = make_corpus(spec_for("c2", n=4000))
     for t in (0.5, 0.7, 0.9):
@@ -237,6 +237,37 @@ def test_prefix_equals_plain(flags):
             assert abs(s - t) < 1e-12
         assert len(a) > 0 or t == 0.9
         assert b.visits < a.visits                        # partial indexing touches less
+
+
+def test_remscore_candidates_by_definition():
+    """Remscore (all-pairs-2, Section 3.2.2) admits y when some indexed
+    component of y meets a component of x processed while the remaining
+    bound was at least t.  With x's components in rank order (densest
+    first), the remaining bound at component k is the prefix sum
+    sum_{i <= k} x_i maxweight_i(V), so the admitted candidates are the pairs
+    y < x whose indexed part meets x where that prefix sum reaches t -- the
+    rule stated here by prefix sums, independently of the oracle's running
+    subtraction."""
+    V = make_corpus(spec_for("c1", n=400))
+    for t in (0.3, 0.5, 0.7):
+        rank, mw, cut = oracle.prefix_index(V, t, l2_clause=True)
+        rows = []
+        for i in range(V.n):
+            c, w = V.row(i)
+            o = np.argsort(rank[c], kind="stable")
+            rows.append((c[o], w[o].astype(np.float64)))
+        indexed = [set(rows[i][0][cut[i]:].tolist()) for i in range(V.n)]
+        cand = 0
+        for x in range(V.n):
+            d, w = rows[x]
+            pre = np.cumsum(w * mw[d].astype(np.float64))
+            adm = set(d[pre >= t].tolist())
+            cand += sum(1 for y in range(x) if adm & indexed[y])
+        res = oracle.join_prefix(V, t, oracle.FLAG_REMSCORE | oracle.FLAG_L2_CLAUSE)
+        base = oracle.join_prefix(V, t, oracle.FLAG_L2_CLAUSE)
+        assert res.candidates == cand
+        assert res.candidates < base.candidates
+        assert set(res.keys().tolist()) == set(base.keys().tolist())
 
 
 def test_unindexed_part_bound():
