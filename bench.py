@@ -290,6 +290,58 @@ def screen_bench(args):
     }
 
 
+VARIANTS = (("partial indexing (all-pairs-1 + bounds)", {}),
+            ("all-pairs-0-array (index_all)", {"index_all": True}),
+            ("local pruning, 2 parts", {"local_parts": 2}),
+            ("local pruning, 4 parts", {"local_parts": 4}),
+            ("remscore", {"remscore": True}))
+
+
+def variants_bench(args):
+    """The algorithm variants on the same corpora and geometry (tile variant 1,
+    16,384-row ranges): the default partial-indexing join; all-pairs-0-array,
+    which indexes every component (the paper's ablation of partial indexing);
+    local pruning over 2 and 4 rank ranges (Lemma 1); remscore.  Every variant
+    returns the same pairs; reported are the join kernel's time and counters."""
+    import numpy as np
+    import torch
+
+    import paper_1402_3010_amd as apss
+    from synth.corpus import make_corpus, spec_for
+
+    out = []
+    # C2 at full size; C3 on its first 300,000 rows (same distributions),
+    # where local pruning's exact rescoring of every local survivor still
+    # finishes in seconds
+    for name, ts, n in (("c2", (0.5, 0.7, 0.9), args.variants_n), ("c3", (0.7,), args.variants_n or 300000)):
+        V = make_corpus(spec_for(name, n=n))
+        dev = (V.n, V.m, torch.from_numpy(V.row_ptr).cuda(), torch.from_numpy(V.col).cuda(),
+               torch.from_numpy(V.val).cuda())
+        for t in ts:
+            t = np.float32(t)
+            base = None
+            for label, kw in VARIANTS:
+                ix = apss.Index.build(dev, t, variant=1, range_rows=16384, **kw)
+                try:
+                    i, _, _ = ix.join(t)
+                    cnt = len(i)
+                    st = ix.stats()
+                finally:
+                    ix.close()
+                if base is None:
+                    base = cnt
+                rec = {"workload": "%s n=%d t=%.1f" % (name, V.n, float(t)), "variant": label,
+                       "kernel_ms": st["ms_candidates"], "join_ms": st["ms_total"],
+                       "posting_visits": st["posting_visits"], "candidates": st["candidates"],
+                       "bound_survivors": st["bound_survivors"], "matches": cnt, "same_pairs_count": cnt == base}
+                out.append(rec)
+                log("variant %s t=%.1f %-40s kernel %8.1f ms  visits %.3e  candidates %.3e  survivors %.3e  matches %d"
+                    % (name, float(t), label, rec["kernel_ms"], rec["posting_visits"], rec["candidates"],
+                       rec["bound_survivors"], cnt))
+        del dev, V
+    return out
+
+
 def serve_bench(args):
     import numpy as np
     import torch
@@ -399,6 +451,9 @@ def main():
     ap.add_argument("--screen-n", type=int, default=None)
     ap.add_argument("--screen-dims", type=int, default=4096)
     ap.add_argument("--screen-steps", type=int, default=3)
+    ap.add_argument("--no-variants", action="store_true", help="skip the algorithm-variant comparison")
+    ap.add_argument("--variants-only", action="store_true")
+    ap.add_argument("--variants-n", type=int, default=None, help="fewer rows for the variant comparison")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-n", type=int, default=None, help="fewer corpus rows for the serving workload")
     ap.add_argument("--serve-slots", type=int, default=2)
@@ -438,6 +493,9 @@ def main():
         return
     if args.screen_only:
         print(json.dumps({"screen": screen_bench(args)}), flush=True)
+        return
+    if args.variants_only:
+        print(json.dumps({"variants": variants_bench(args)}), flush=True)
         return
     t = np.float32(args.t if args.t is not None else CONFIGS[args.config]["t"][0])
     spec = spec_for(args.config, n=args.n)
@@ -539,6 +597,8 @@ def main():
     del V
     if not args.no_screen:
         out["screen"] = screen_bench(args)
+    if not args.no_variants:
+        out["variants"] = variants_bench(args)
     if not args.no_serve:
         sv = serve_bench(args)
         out["serve"] = sv

@@ -115,6 +115,9 @@ def load(path: str = LIB_PATH):
     lib.apss_join_device.restype = ctypes.c_int
     lib.apss_join_device_noalloc.argtypes = [P, f32, P, P, P, i64, ctypes.POINTER(i64)]
     lib.apss_join_device_noalloc.restype = ctypes.c_int
+    # test hook outside the ABI header: the screen's raw head products
+    lib.apss_probe_screen_products.argtypes = [P, P, i64, P, P]
+    lib.apss_probe_screen_products.restype = ctypes.c_int
     lib.apss_join.argtypes = [P, f32, ctypes.POINTER(Pairs)]
     lib.apss_join.restype = ctypes.c_int
     lib.apss_query.argtypes = [P, i64, P, P, P, ctypes.c_int, P, f32, ctypes.POINTER(Pairs)]
@@ -284,6 +287,18 @@ def join_device_noalloc(h: int, t: float, out_i, out_j, out_sim) -> int:
         raise e
     _check(rc)
     return cnt.value
+
+
+def probe_screen_products(h: int, rows):
+    """Test hook (not part of include/apss.h): the bf16 MFMA screen's float
+    head products H~ of the given rows (S x S, upper triangle) and their
+    rounded-up head norms, on an index built with screen_dims > 0."""
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    S = len(rows)
+    H = np.zeros((S, S), np.float32)
+    N = np.zeros(S, np.float32)
+    _check(load().apss_probe_screen_products(h, rows.ctypes.data, S, H.ctypes.data, N.ctypes.data))
+    return H, N
 
 
 def _query_args(Q_row_ptr, Q_col, Q_val, t_per_row):

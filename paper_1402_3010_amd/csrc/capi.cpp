@@ -729,7 +729,7 @@ int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, in
       CHK(ws.s_cand.reserve(std::max<int64_t>(1 << 16, 4 * S)), "alloc screen");
       for (int attempt = 0; attempt < 2; ++attempt) {
         CHK(fill_u64((uint64_t*)ws.s_cnt.p, 0ull, 1, s), "fill");
-        ScreenArgs A;
+        ScreenArgs A{};
         A.X = ws.s_X.p;
         A.ld = ld;
         A.nh = ws.s_nh.p;

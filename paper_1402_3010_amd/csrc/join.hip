@@ -138,9 +138,10 @@ struct Smem {
   int64_t item;
   unsigned long long cnt[C_NUM];
   uint32_t acc[C::QT * C::CB];
-  // remscore: admission bits, of row y - block start (bit = query slot) on
-  // the block path and of hash slot h (word h / 32) on the hashed path
-  uint32_t adm[REM ? C::CB : 1];
+  // remscore: one admission bit per accumulator slot -- bit (y - block
+  // start) * QT + query slot on the block path, bit h (hash slot) on the
+  // hashed path; cleared after each filter pass
+  uint32_t adm[REM ? C::QT * C::CB / 32 : 1];
   float qd[C::QT * C::RD];
   Seg seg[C::QB];
   int32_t segpre[C::QB + 1];
@@ -206,8 +207,19 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   const __amdgpu_buffer_rsrc_t prs = make_rsrc(a.post4, a.post4_bytes);
   // the accumulators start at zero and every item leaves them at zero
   for (int e = tid; e < QT * CB; e += NT) sm.acc[e] = 0u;
+  constexpr int ADMW = QT * CB / 32;  // admission words (remscore)
   if constexpr (REM)
-    for (int e = tid; e < CB; e += NT) sm.adm[e] = 0u;
+    for (int e = tid; e < ADMW; e += NT) sm.adm[e] = 0u;
+  // every filter pass leaves the admission bits at zero
+  auto clear_adm = [&]() {
+    if constexpr (REM)
+      for (int e = tid; e < ADMW; e += NT) sm.adm[e] = 0u;
+  };
+  // admission bit of (row offset in the block, query slot) on the block path
+  auto admit_row = [&](uint32_t yl, int qi) {
+    const uint32_t b = yl * (uint32_t)QT + (uint32_t)qi;
+    atomicOr(&sm.adm[b >> 5], 1u << (b & 31u));
+  };
 
   // Persistent loop over work items (corpus range R, query tile T).  The
   // queue of XCD x holds the ranges R = x, x + 8, ... in order, so the
@@ -694,8 +706,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             if (kk[g] && !retry) {
               hkey[h] = 0u;
               hval[h] = 0u;
-              if constexpr (REM) atomicAnd(&sm.adm[h >> 5], ~(1u << (h & 31)));
-            }
+              }
           }
         }
       } else {
@@ -745,7 +756,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           if (kk && !retry) {
             hkey[h] = 0u;
             hval[h] = 0u;
-            if constexpr (REM) atomicAnd(&sm.adm[h >> 5], ~(1u << (h & 31)));
           }
         }
       }
@@ -754,7 +764,10 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       const int qc = uni(sm.qcount);
       __syncthreads();
       if (qc > 0) drain();
-      if (!o) break;
+      if (!o) {
+        clear_adm();
+        break;
+      }
     }
   }
 
@@ -964,7 +977,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           const int ab = tqi[j] * CB - (int)blk0;
           atomicAdd(&sm.acc[ab + (int)t0[j].y], fixp(tw[j], t0[j].w));
           if constexpr (REM)
-            if (tadm[j]) atomicOr(&sm.adm[(int)t0[j].y - (int)blk0], 1u << tqi[j]);
+            if (tadm[j]) admit_row((uint32_t)(t0[j].y - (uint32_t)blk0), tqi[j]);
           ++c_tail;
           ++pos;
           uint32_t ny = pos < end ? t1y[j] : 0xFFFFFFFFu;
@@ -972,7 +985,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             const Post p = a.post[pos];
             atomicAdd(&sm.acc[ab + (int)p.y], fixp(tw[j], p.w));
             if constexpr (REM)
-              if (tadm[j]) atomicOr(&sm.adm[(int)p.y - (int)blk0], 1u << tqi[j]);
+              if (tadm[j]) admit_row((uint32_t)(p.y - (uint32_t)blk0), tqi[j]);
             ++c_tail;
             ++pos;
             ny = pos < end ? a.post[pos].y : 0xFFFFFFFFu;
@@ -991,7 +1004,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         // a lane past the slice adds zero to a slot of its row (no branch)
         atomicAdd(&sm.acc[qi * CB + (int)(p & (CB - 1))], live ? packed_product(qw, p) : 0u);
         if constexpr (REM)
-          if (live && (qw >> 31)) atomicOr(&sm.adm[p & (CB - 1)], 1u << qi);
+          if (live && (qw >> 31)) admit_row(p & (uint32_t)(CB - 1), qi);
       });
       // long segments: wave w takes segments w, w + NW, ... in chunks of 64
       // entries (one per lane).  Lane i holds the descriptor of the wave's
@@ -1056,7 +1069,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             const uint32_t w = lane < ccnt[u] ? packed_product(cq[u], p[u]) : 0u;
             atomicAdd(&sm.acc[and_or(p[u], (uint32_t)(CB - 1), cab[u])], w);
             if constexpr (REM)
-              if ((cq[u] >> 31) && lane < ccnt[u]) atomicOr(&sm.adm[p[u] & (CB - 1)], 1u << (cab[u] / CB));
+              if ((cq[u] >> 31) && lane < ccnt[u]) admit_row(p[u] & (uint32_t)(CB - 1), (int)(cab[u] / CB));
           }
         };
         uint32_t aoff[UL], aq[UL], pa[UL], boff[UL], bq[UL], pb[UL], aab[UL], bab[UL];
@@ -1113,7 +1126,10 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 #pragma unroll
         for (int qi = 0; qi < QT; ++qi) av[qi] = sm.acc[qi * CB + yl];
         uint32_t abits = ~0u;  // remscore: slots whose candidate was admitted
-        if constexpr (REM) abits = sm.adm[yl];
+        if constexpr (REM) {
+          const uint32_t b = (uint32_t)yl * (uint32_t)QT;
+          abits = sm.adm[b >> 5] >> (b & 31u);
+        }
         // the bounds of all slots first, without branches; the rare
         // survivors are then queued slot by slot
         uint32_t wbits = 0u, ncand = 0u;
@@ -1154,7 +1170,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         }
 #pragma unroll
         for (int qi = 0; qi < QT; ++qi) sm.acc[qi * CB + yl] = ((keep >> qi) & 1u) ? av[qi] : 0u;
-        if constexpr (REM) sm.adm[yl] = abits & keep;
         c_cand += ncand;
       }
     };
@@ -1167,7 +1182,10 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       const int qc = uni(sm.qcount);
       __syncthreads();
       if (qc > 0 && (o || !defer || b + 1 == b_end || qc >= SQ / 2)) drain();
-      if (!o) break;
+      if (!o) {
+        clear_adm();
+        break;
+      }
     }
   }
 

@@ -40,6 +40,11 @@ struct ScreenArgs {
   uint64_t* out;       // [cap] candidate keys (min id << bj | max id)
   int64_t cap;
   unsigned long long* count;
+  // non-NULL: instead of testing the threshold, write every accumulated
+  // head product of the tiles to dump[row * dump_ld + col] (positions in the
+  // packed order); a check of the screen's error bound, not part of the join
+  float* dump;
+  int64_t dump_ld;
 };
 hipError_t launch_screen_mfma(const ScreenArgs& a, hipStream_t s);
 

@@ -114,6 +114,7 @@ constexpr int kStepK = 32;
 
 __device__ __forceinline__ int swz(int row, int c) { return row * 4 + (c ^ ((row >> 2) & 3)); }
 
+template <bool DUMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_screen_mfma(ScreenArgs a, int64_t chunk) {
   __shared__ u32x4 As[2][kScreenTile * 4];
   __shared__ u32x4 Bs[2][kScreenTile * 4];
@@ -203,6 +204,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     compute(1);
     sts(0, r0);
     __syncthreads();
+  }
+
+  if constexpr (DUMP) {
+    // the accumulators themselves, for a check of the error bound
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t b = b0 + wc + 32 * j + (lane & 31);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t ar = a0 + wr + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          a.dump[ar * a.dump_ld + b] = acc[i][j][r];
+        }
+    }
+    return;
   }
 
   // epilogue: threshold test and compaction by wave ballot
@@ -314,12 +331,15 @@ hipError_t launch_screen_pack(const int64_t* rp, const RComp* rc, const int32_t*
 
 hipError_t launch_screen_mfma(const ScreenArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
-  if (!a.X || !a.nh || !a.sid || !a.tiles || !a.out || !a.count || a.ld <= 0 || a.ld % kScreenK)
-    return hipErrorInvalidValue;
+  if (!a.X || !a.tiles || a.ld <= 0 || a.ld % kScreenK) return hipErrorInvalidValue;
+  if (!a.dump && (!a.nh || !a.sid || !a.out || !a.count)) return hipErrorInvalidValue;
   const int64_t chunk = (a.ntiles + 7) / 8;
   const int64_t grid = 8 * chunk;
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_screen_mfma, dim3((unsigned)grid), dim3(256), 0, s, a, chunk);
+  if (a.dump)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_screen_mfma<true>), dim3((unsigned)grid), dim3(256), 0, s, a, chunk);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_screen_mfma<false>), dim3((unsigned)grid), dim3(256), 0, s, a, chunk);
   return hipGetLastError();
 }
 
