@@ -626,7 +626,11 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     stream_short(sseg, ns, L, [&](int qi, uint32_t p, uint32_t qw, bool live) {
       if (!live) return;
       const uint32_t key = (((uint32_t)qi << 16) | ((p - (uint32_t)rbeg) & 0xFFFFu)) + 1u;
+      // double hashing: a second multiplicative hash gives an odd step, so
+      // the probe sequence visits every slot of the power-of-two table (which
+      // is never full) and keys that collide once part at the next probe
       uint32_t h = (key * 0x9E3779B1u) >> (32 - HBITS);
+      const uint32_t step = ((key * 0x85EBCA77u) >> (32 - HBITS)) | 1u;
       for (;;) {
         const uint32_t old = atomicCAS(&hkey[h], 0u, key);
         if (old == 0u || old == key) {
@@ -635,7 +639,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             if (qw >> 31) atomicOr(&sm.adm[h >> 5], 1u << (h & 31u));
           break;
         }
-        h = (h + 1u) & (uint32_t)(HS - 1);
+        h = (h + step) & (uint32_t)(HS - 1);
       }
     });
     __syncthreads();
