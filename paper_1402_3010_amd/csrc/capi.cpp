@@ -267,10 +267,18 @@ int build_lists(apss_index* ix) {
                     ix->rs.p, ix->rows.mw.p, nidx.p, s),
       "cutoff");
   CHK(exclusive_scan_i64(nidx.p, n, scan_tmp.p, total.p, s), "scan");
+  // the largest unindexed-part norm: the hashed filter's test without row statistics
+  DBuf<uint32_t> pmax;
+  CHK(pmax.alloc(1), "alloc");
+  CHK(fill_u32(pmax.p, 0u, 1, s), "fill");
+  CHK(launch_max_pnrm(ix->rs.p, n, pmax.p, s), "max norm");
   int64_t P = 0;
+  uint32_t pmax_bits = 0u;
   CHK(hipMemcpyAsync(&P, total.p, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read P");
+  CHK(hipMemcpyAsync(&pmax_bits, pmax.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read max norm");
   CHK(hipStreamSynchronize(s), "read P");
   ix->P = P;
+  memcpy(&ix->pnrm_max, &pmax_bits, sizeof(float));
   if (4 * (P + kPost4Pad) >= (1ll << 32)) {
     set_error("index too large: %lld postings (the packed lists must stay below 4 GiB)", (long long)P);
     return APSS_EINVAL;
@@ -478,7 +486,11 @@ int plan_layout(apss_index* ix, const QuerySet& Q, int triangle, JoinLayout& L) 
       }
     }
   }
-  L.G = ix->grid[variant];
+  // no more workgroups than work items: a small batch leaves the rest of
+  // the device to work running beside it (another serving slot)
+  int64_t items = 0;
+  for (int x = 0; x < 8; ++x) items += L.cum[(size_t)(x * (L.nrx + 1) + L.nrx)];
+  L.G = (int)std::max<int64_t>(1, std::min<int64_t>(ix->grid[variant], items));
   // per-workgroup cursor space for tiles too large to stage in LDS
   L.wg_stride = 2 * std::max<int64_t>(L.tiles.max_nnz, 1);
   return APSS_OK;
@@ -492,6 +504,7 @@ void bind_plan(apss_index* ix, const QuerySet& Q, int triangle, float t, const f
   a.rp = ix->rows.rp.p;
   a.rc = ix->rows.rc.p;
   a.rs = ix->rs.p;
+  a.pnrm_max = ix->pnrm_max;
   a.off = ix->off.p;
   a.post = ix->post.p;
   a.post4 = ix->post4.p;

@@ -159,6 +159,15 @@ __global__ void k_cutoff(const int64_t* __restrict__ rp, const RComp* __restrict
   }
 }
 
+// Largest unindexed-part norm over the rows (norms are >= 0, so their bit
+// patterns order like the values).
+__global__ void k_max_pnrm(const RowStat* __restrict__ rs, int64_t n, uint32_t* __restrict__ out) {
+  uint32_t m = 0u;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    m = max(m, __float_as_uint(rs[r].pnrm));
+  if (m) atomicMax(out, m);
+}
+
 // Indexed components in row-major order -> (key = rank, value = y << 32 | weight bits).
 __global__ void k_emit_indexed(const int64_t* __restrict__ rp, const RComp* __restrict__ rc,
                                const RowStat* __restrict__ rs, const int64_t* __restrict__ ibase, int64_t n,
@@ -343,6 +352,12 @@ hipError_t launch_count_ranks(const uint64_t* keys, int64_t P, int64_t* cnt, hip
 
 hipError_t launch_unpack_post(const uint64_t* vals, int64_t P, Post* post, hipStream_t s) {
   LAUNCH(k_unpack_post, P, vals, P, post);
+  return hipSuccess;
+}
+
+hipError_t launch_max_pnrm(const RowStat* rs, int64_t n, uint32_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LAUNCH(k_max_pnrm, n, rs, n, out);
   return hipSuccess;
 }
 

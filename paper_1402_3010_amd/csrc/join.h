@@ -14,6 +14,7 @@ struct JoinArgs {
   const int64_t* rp;      // [n+1] row offsets of the rank-space rows
   const RComp* rc;        // [nnz] components, densest dimension first
   const RowStat* rs;      // [n]
+  float pnrm_max;         // max over rows of rs[y].pnrm
   const int64_t* off;     // [m+1] list offsets by rank
   const Post* post;       // [P+2] list entries, vector ids ascending within a list; 2 padding entries
   const uint32_t* post4;  // [P+kPost4Pad] the same entries packed: id mod 2^16 | weight in 2^-15 units (rounded up) << 16

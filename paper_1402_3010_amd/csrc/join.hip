@@ -126,6 +126,7 @@ struct Smem {
   float qpn[C::QT];  // bound on the query's part in the corpus rows' unindexed dimensions
   float qt[C::QT];
   float4 qb[C::QT];  // filter bounds of each query, times 2^30: threshold - slack, max weight, length * max weight, qpn
+  float2 rtest;      // the tile's lowest qb.x (less 4,096 units) and highest qb.w: a row test that every slot's L2 bound implies
   int32_t qlen[C::QT];
   int32_t qhead[C::QT];
   int32_t wsum[C::NT / 64];
@@ -388,6 +389,18 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   if (vmine) atomicAdd(&sm.vtot, vmine);
   __syncthreads();
   if (staged && tid < qn) sm.qhead[tid] = find_head(sm.qrow + (sm.qoff[tid] - qbase), sm.qlen[tid]);
+  if (tid == 0) {
+    // a slot's L2 bound A + qb.w * pnrm >= qb.x implies the row test
+    // amax + rtest.y * pnrm >= rtest.x for the row's largest score amax
+    // (float sums and products are monotone; the 4,096 units, 4e-6 of a
+    // score, cover a fused multiply-add on one side only)
+    float tmin = 3.0e38f, wmax = 0.0f;
+    for (int qi = 0; qi < qn; ++qi) {
+      tmin = fminf(tmin, sm.qb[qi].x);
+      wmax = fmaxf(wmax, sm.qb[qi].w);
+    }
+    sm.rtest = make_float2(tmin - 4096.0f, wmax);
+  }
   __syncthreads();
 
   // q[r] for the query in slot qi (0 if absent)
@@ -658,7 +671,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         for (int h0 = 0; h0 < HS; h0 += G * NT) {
           uint32_t kk[G], hv[G];
           int64_t yv[G];
-          bool ok[G];
+          bool ok[G], pre[G];
           RowStat stg[G];
 #pragma unroll
           for (int g = 0; g < G; ++g) {
@@ -669,7 +682,11 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             yv[g] = rbeg + (int64_t)((kk[g] - 1u) & 0xFFFFu);
             ok[g] = kk[g] != 0u && yv[g] < a.n && !(a.triangle && yv[g] >= q0 + qi);
             if constexpr (REM) ok[g] = ok[g] && ((sm.adm[h >> 5] >> (h & 31)) & 1u);
-            stg[g] = a.rs[ok[g] ? yv[g] : 0];
+            // the L2 bound with the largest unindexed-part norm of any row:
+            // a candidate that fails it cannot survive and needs no row statistics
+            const float4 qbq = sm.qb[ok[g] ? qi : 0];
+            pre[g] = ok[g] && (float)hv[g] + qbq.w * a.pnrm_max >= qbq.x - 4096.0f;
+            stg[g] = a.rs[pre[g] ? yv[g] : 0];
           }
 #pragma unroll
           for (int g = 0; g < G; ++g) {
@@ -679,7 +696,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             const int yl = (int)((kk[g] - 1u) & 0xFFFFu);
             const uint32_t av = hv[g];
             uint32_t packed = 0u;
-            if (ok[g]) {
+            if (pre[g]) {
               const RowStat st = stg[g];
               const int ylen = st.len;
               packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
@@ -688,8 +705,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
               const float thr = qb.x, qm = qb.y;
               want = ((float)ylen * qm >= thr) && (A + min_nonneg((float)st.cut * qm, qb.z) * st.pmw >= thr) &&
                      (A + qb.w * st.pnrm >= thr);
-              ++c_cand;
             }
+            if (ok[g]) ++c_cand;
             const uint64_t wm = __ballot(want);
             if (wm) {
               int qb = 0;
@@ -729,14 +746,17 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             bool adm_ok = true;
             if constexpr (REM) adm_ok = (sm.adm[h >> 5] >> (h & 31)) & 1u;
             if (adm_ok && y < a.n && !(a.triangle && y >= q0 + qi)) {
-              const RowStat st = a.rs[y];
-              const int ylen = st.len;
-              packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
-              const float A = (float)av;  // accumulator units, as the bounds
               const float4 qb = sm.qb[qi];
-              const float thr = qb.x, qm = qb.y;
-              want = ((float)ylen * qm >= thr) && (A + min_nonneg((float)st.cut * qm, qb.z) * st.pmw >= thr) &&
-                     (A + qb.w * st.pnrm >= thr);
+              const float A = (float)av;  // accumulator units, as the bounds
+              // the L2 bound with the largest unindexed-part norm of any row first
+              if (A + qb.w * a.pnrm_max >= qb.x - 4096.0f) {
+                const RowStat st = a.rs[y];
+                const int ylen = st.len;
+                packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);
+                const float thr = qb.x, qm = qb.y;
+                want = ((float)ylen * qm >= thr) && (A + min_nonneg((float)st.cut * qm, qb.z) * st.pmw >= thr) &&
+                       (A + qb.w * st.pnrm >= thr);
+              }
               ++c_cand;
             }
           }
@@ -1134,19 +1154,31 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           const uint32_t b = (uint32_t)yl * (uint32_t)QT;
           abits = sm.adm[b >> 5] >> (b & 31u);
         }
-        // the bounds of all slots first, without branches; the rare
-        // survivors are then queued slot by slot
-        uint32_t wbits = 0u, ncand = 0u;
+        // the candidates (live slots), and the row's largest score
+        uint32_t lbits = 0u, amax = 0u;
 #pragma unroll
         for (int qi = 0; qi < QT; ++qi) {
-          const float4 qb = sm.qb[qi];
           bool live = FULL ? (av[qi] != 0u) : ((av[qi] != 0u) & (qi >= qlo));
           if constexpr (REM) live = live & (((abits >> qi) & 1u) != 0u);
-          const float A = (float)av[qi];  // accumulator units, as the bounds
-          const bool want = live & (ylf * qb.y >= qb.x) & (A + min_nonneg(cutf * qb.y, qb.z) * st.pmw >= qb.x) &
-                            (A + qb.w * st.pnrm >= qb.x);
-          ncand += live ? 1u : 0u;
-          wbits |= want ? (1u << qi) : 0u;
+          lbits |= live ? (1u << qi) : 0u;
+          amax = max(amax, av[qi]);
+        }
+        uint32_t ncand = (uint32_t)__popc(lbits);
+        // the bounds of all slots, without branches, unless no row of the
+        // wave passes the row test (the usual case: survivors are rare);
+        // the survivors are then queued slot by slot
+        uint32_t wbits = 0u;
+        const float2 rt = sm.rtest;
+        if (__ballot((float)amax + rt.y * st.pnrm >= rt.x)) {
+#pragma unroll
+          for (int qi = 0; qi < QT; ++qi) {
+            const float4 qb = sm.qb[qi];
+            const bool live = (lbits >> qi) & 1u;
+            const float A = (float)av[qi];  // accumulator units, as the bounds
+            const bool want = live & (ylf * qb.y >= qb.x) & (A + min_nonneg(cutf * qb.y, qb.z) * st.pmw >= qb.x) &
+                              (A + qb.w * st.pnrm >= qb.x);
+            wbits |= want ? (1u << qi) : 0u;
+          }
         }
         uint32_t keep = 0u;  // queue full: these slots stay for the next pass
         if (__ballot(wbits != 0u)) {

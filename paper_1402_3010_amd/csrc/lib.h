@@ -164,6 +164,7 @@ struct apss_index {
   int64_t n = 0, m = 0, nnz = 0, P = 0;
   float t_build = 0.0f;
   int32_t H = 0;
+  float pnrm_max = 0.0f;    // largest unindexed-part norm over the rows (RowStat.pnrm)
   int variant = 1;          // tile variant of the join kernel
   int64_t range_rows = 0;   // corpus rows per work-item range
   int32_t head_cut = 0;     // > 0: the unindexed part of every row is its components of rank < head_cut
