@@ -339,12 +339,77 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) hn[j] = 0;
   int32_t vmine = 0;  // this thread's share of the item's list entries
-  if (b_begin < b_end) {
+  if (b_begin < b_end && staged) {
+    // A staged tile has at most QB = KMAX * NT components: every component
+    // load is issued first, then every list-offset load, then the LDS
+    // writes, so the loads' latencies overlap instead of adding up per
+    // component.  Live segments take their places by one atomic per wave.
+    RComp cc[KMAX];
+    int cq[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      const int k = j * NT + tid;
+      cc[j] = k < tile_nnz ? a.qrc[qbase + k] : RComp{0x7FFFFFFF, 0.0f};
+      cq[j] = k < tile_nnz ? find_slot(qbase + k) : 0;
+    }
+    uint32_t p0[KMAX], p1[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      const int k = j * NT + tid;
+      const int32_t r = cc[j].r;
+      p0[j] = 0u;
+      p1[j] = 0u;
+      if (k < tile_nnz) {
+        // dense lists by block offsets, sparse ones by range offsets
+        const bool dense = r < a.H;
+        const uint32_t* t0 = dense ? a.hoff + b_begin * (int64_t)a.H + r : a.toff + R * (int64_t)a.m_tail + (r - a.H);
+        const uint32_t* t1 = dense ? a.hoff + b_end * (int64_t)a.H + r : a.toff + (R + 1) * (int64_t)a.m_tail + (r - a.H);
+        p0[j] = *t0;
+        p1[j] = *t1;
+        // the next block's segment end of a dense list (b_begin + 1 <= nb)
+        hn[j] = dense ? a.hoff[(b_begin + 1) * (int64_t)a.H + r] : 0u;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      const int k = j * NT + tid;
+      const bool valid = k < tile_nnz;
+      const RComp c = cc[j];
+      const int qi = cq[j];
+      bool admits = true;  // remscore: the component admits new candidates
+      if constexpr (REM) admits = valid && qbase + k - sm.qoff[qi] >= (int64_t)a.qadm[q0 + qi];
+      if (valid && c.r < RD) sm.qd[qi * RD + c.r] = c.w;
+      // no list entry in the item's corpus range, or a rank outside the item's part
+      const bool dead = !valid || p1[j] == p0[j] || c.r < plo || c.r >= phi;
+      vmine += dead ? 0 : (int32_t)(p1[j] - p0[j]);
+      if (valid) {
+        sm.qrow[k] = c;
+        sm.cqi[k] = (uint8_t)(qi | (admits ? 0x80 : 0));
+        // the block path loads the first entry's vector id of a sparse list
+        // once the item is known to take that path
+        sm.cur[k] = make_uint2(dead ? kDead : p0[j], 0u);
+      }
+      if (dead) hn[j] = 0u;
+      // the component's entries in the whole range, for a hashed item
+      // (whose segments are all short enough for the 16-bit length)
+      const uint64_t m = __ballot(!dead);
+      int base = 0;
+      if (lane == 0 && m) base = atomicAdd(&sm.nshort, (int)__popcll(m));
+      base = __shfl(base, 0);
+      if (!dead) {
+        Seg sg;
+        sg.pos = p0[j];
+        sg.lenq = ((p1[j] - p0[j]) & 0xFFFFu) | ((uint32_t)qi << 16);
+        // bit 31 (remscore): the component admits; the 24-bit product ignores it
+        sg.q = q15(c.w) | (REM && admits ? 0x80000000u : 0u);
+        sm.seg[QB - 1 - (base + (int)__popcll(m & lt))] = sg;
+      }
+    }
+  } else if (b_begin < b_end) {
+    // tiles too large to stage: list cursors in the workgroup's global space
     for (int64_t k = tid; k < tile_nnz; k += NT) {
       const RComp c = a.qrc[qbase + k];
       const int qi = find_slot(qbase + k);
-      bool admits = true;  // remscore: the component admits new candidates
-      if constexpr (REM) admits = qbase + k - sm.qoff[qi] >= (int64_t)a.qadm[q0 + qi];
       if (c.r < RD) sm.qd[qi * RD + c.r] = c.w;
       uint32_t p0, p1, ny = 0;
       if (c.r < a.H) {
@@ -353,40 +418,20 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       } else {
         p0 = a.toff[R * (int64_t)a.m_tail + (c.r - a.H)];
         p1 = a.toff[(R + 1) * (int64_t)a.m_tail + (c.r - a.H)];
-        // the first entry's vector id is needed only on the block path; for
-        // staged tiles it is loaded once the item is known to take that path
-        if (!staged) ny = (int64_t)p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
+        ny = (int64_t)p0 < a.off[c.r + 1] ? a.post[p0].y : 0xFFFFFFFFu;
       }
       // no list entry in the item's corpus range, or a rank outside the item's part
       const bool dead = p1 == p0 || c.r < plo || c.r >= phi;
       if (dead) p1 = p0;
       vmine += (int32_t)(p1 - p0);
-      if (staged) {
-        sm.qrow[k] = c;
-        sm.cqi[k] = (uint8_t)(qi | (admits ? 0x80 : 0));
-        // the component's entries in the whole range, for a hashed item
-        // (whose segments are all short enough for the 16-bit length)
-        if (!dead) {
-          Seg sg;
-          sg.pos = p0;
-          sg.lenq = ((p1 - p0) & 0xFFFFu) | ((uint32_t)qi << 16);
-          // bit 31 (remscore): the component admits; the 24-bit product ignores it
-          sg.q = q15(c.w) | (REM && admits ? 0x80000000u : 0u);
-          sm.seg[QB - 1 - atomicAdd(&sm.nshort, 1)] = sg;
-        }
-        sm.cur[k] = make_uint2(dead ? kDead : p0, ny);
-        if (c.r < a.H && !dead) {
-#pragma unroll
-          for (int j = 0; j < KMAX; ++j)
-            if (k == (int64_t)j * NT + tid) hn[j] = a.hoff[(b_begin + 1) * (int64_t)a.H + c.r];
-        }
-      } else {
-        gcur[2 * k] = dead ? kDead : p0;
-        gcur[2 * k + 1] = ny;
-      }
+      gcur[2 * k] = dead ? kDead : p0;
+      gcur[2 * k + 1] = ny;
     }
   }
-  if (vmine) atomicAdd(&sm.vtot, vmine);
+  // one atomic per wave for the item's entry count
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) vmine += __shfl_xor(vmine, o, 64);
+  if (lane == 0 && vmine) atomicAdd(&sm.vtot, vmine);
   __syncthreads();
   if (staged && tid < qn) sm.qhead[tid] = find_head(sm.qrow + (sm.qoff[tid] - qbase), sm.qlen[tid]);
   if (tid == 0) {
