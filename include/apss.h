@@ -244,7 +244,10 @@ int apss_autotune(apss_index* idx, float t, double budget_ms, const char* cache_
  * APSS_EBUSY instead of queueing while the reservations would exceed
  * memory_budget or max_pending requests are held.  A batch whose pairs
  * outgrow their reservation still completes (its buffers grow; counted in
- * apss_server_stats.regrows).
+ * apss_server_stats.regrows), and its slot releases the grown buffers when
+ * it ends, so that between such batches the slots hold what the
+ * reservations cover; apss_server_stats.device_bytes reports what each slot
+ * holds.
  *
  * All server entry points are thread-safe, except apss_server_destroy, which
  * must not overlap any other call on the same server. */

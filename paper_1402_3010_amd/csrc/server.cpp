@@ -289,6 +289,21 @@ void worker(apss_server* S, int slot) {
     if (more) S->cv_work.notify_one();
     const int64_t regrows0 = ws.regrows;
     run_batch(S, ws, rows, hs, batch);
+    if (ws.regrows != regrows0) {
+      // the batch's pairs outgrew its reservation and its buffers grew
+      // beyond what the budget charged for: release them (after the slot's
+      // stream has drained), so the slot holds no more than later batches
+      // reserve; the next batch allocates its own size again
+      (void)hipStreamSynchronize(ws.stream);
+      ws.raw_key.release();
+      ws.raw_sim.release();
+      ws.ss.k2.release();
+      ws.ss.v32b.release();
+      ws.ss.hist.release();
+      ws.ss.scan.release();
+      ws.ss.v64a.release();
+      ws.ss.v64b.release();
+    }
     {
       std::lock_guard<std::mutex> lk(S->mu);
       const Clock::time_point now = Clock::now();

@@ -210,3 +210,30 @@ def test_submit_validation_and_edge_requests(apss, corpus, index):
         assert_parity(i, j, s, oracle.query(V, good, t=0.6), 0.6, good, V)
         st = srv.stats()
         assert st["failed"] == 0 and st["submitted"] == 4
+
+
+def test_regrown_slot_buffers_are_released(apss):
+    """A batch whose pairs outgrow its reservation completes, and its slot
+    gives the grown buffers back when it ends."""
+    from synth.corpus import from_rows
+    base = make_corpus(spec_for("c1", n=1))
+    row = dict(zip(base.row(0)[0].tolist(), base.row(0)[1].tolist()))
+    other = make_corpus(spec_for("c1", n=2000))
+    rows = [row] * 3000 + [dict(zip(*[a.tolist() for a in other.row(k)])) for k in range(other.n)]
+    V = from_rows(rows, base.m)
+    Q = from_rows([row] * 40, base.m)            # 40 x 3000 = 120,000 pairs
+    ix = apss.Index.build(V, T_BUILD)
+    try:
+        with apss.Server(ix, slots=1, pairs_per_query=1) as srv:
+            i, j, s, _ = srv.poll(srv.submit(Q, t=0.9))
+            st = srv.stats()
+            small = srv.poll(srv.submit(Q.take_rows(np.arange(1)), t=0.9))
+            st2 = srv.stats()
+    finally:
+        ix.close()
+    assert len(i) == 40 * 3000
+    assert st["regrows"] >= 1
+    # the slot holds far less than the 120,000-pair buffers it grew to
+    assert st["device_bytes"][0] < 12 * 120000
+    assert len(small[0]) == 3000 and st2["failed"] == 0
+    assert_parity(i, j, s, oracle.query(V, Q, t=0.9), 0.9, Q, V)
