@@ -376,7 +376,8 @@ def serve_bench(args):
 
     pool = make_queries(V, 32768, spec, seed=2005)
     pool_fresh = make_queries(V, 32768, spec, seed=3005, frac_copies=0.0)
-    srv = apss.Server(ix, slots=args.serve_slots, max_batch_queries=4096)
+    srv = apss.Server(ix, slots=args.serve_slots, max_batch_queries=args.serve_max_batch,
+                      split_queries=args.serve_split)
     drv = ServeDriver(apss, srv)
     # warm-up, then saturation: all requests arrive at once
     drv.run(requests(pool, 8), [0.0] * 8)
@@ -398,15 +399,20 @@ def serve_bench(args):
         st1 = srv.stats()
         lat = [r[1] for r in res]
         nq = sum(Q.n for Q, _ in reqs)
+        small = [r[1] for r in res if reqs[r[0]][0].n <= 256]
+        large = [r[1] for r in res if reqs[r[0]][0].n > 256]
         point = {"load": frac, "rate_rps": rate, "requests": n_req, "queries": nq,
                  "qps": nq / el, "rps": n_req / el, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                 "p99_ms_requests_le_256_queries": percentile(small, 99),
+                 "p99_ms_requests_gt_256_queries": percentile(large, 99),
                  "mean_batch_requests": float(np.mean([r[2]["batch_requests"] for r in res])),
                  "batches": st1["batches"] - st0["batches"],
                  "overlapped_batches": st1["overlapped_batches"] - st0["overlapped_batches"],
                  "busy_retries": busy, "pairs": int(sum(r[3] for r in res))}
         curve.append(point)
-        log("serve load %.2f: %.1f req/s offered, %.0f queries/s, p50 %.1f ms, p99 %.1f ms"
-            % (frac, rate, point["qps"], point["p50_ms"], point["p99_ms"]))
+        log("serve load %.2f: %.1f req/s offered, %.0f queries/s, p50 %.1f ms, p99 %.1f ms "
+            "(requests of <= 256 queries: p99 %.1f ms)"
+            % (frac, rate, point["qps"], point["p50_ms"], point["p99_ms"], point["p99_ms_requests_le_256_queries"] or 0.0))
     # the middle load once more on queries without corpus copies
     frac = args.serve_load[len(args.serve_load) // 2]
     rate = frac * sat_rps
@@ -426,6 +432,8 @@ def serve_bench(args):
                     "t_build=0.5; requests of 1..4096 queries (log-uniform), query nnz lognormal mean 100, "
                     "10%% perturbed corpus copies, per-request t ~ U[0.5, 0.95], Poisson arrivals" % (V.n, V.m),
         "slots": args.serve_slots,
+        "split_queries": args.serve_split,
+        "max_batch_queries": args.serve_max_batch,
         "qps": mid["qps"], "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"], "at_load": mid["load"],
         "saturation_qps": sat_qps, "saturation_rps": sat_rps,
         "curve": curve,
@@ -457,6 +465,9 @@ def main():
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-n", type=int, default=None, help="fewer corpus rows for the serving workload")
     ap.add_argument("--serve-slots", type=int, default=2)
+    ap.add_argument("--serve-max-batch", type=int, default=4096, help="queries merged into one batch at most")
+    ap.add_argument("--serve-split", type=int, default=0,
+                    help="queue requests of more rows as pieces of at most this many rows (0: whole requests)")
     ap.add_argument("--serve-requests", type=int, default=120, help="requests in the saturation burst")
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="length of each open-loop run")
     ap.add_argument("--serve-load", type=float, nargs="+", default=[0.3, 0.6, 0.9],

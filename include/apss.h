@@ -258,11 +258,16 @@ typedef struct apss_server apss_server;
 typedef struct {
   int32_t struct_size;        /* sizeof(apss_server_opts) */
   int32_t slots;              /* batches in flight at once, 1..APSS_SERVER_MAX_SLOTS (default 2) */
-  int64_t max_batch_queries;  /* queries merged into one batch, and the largest request (default 4096) */
+  int64_t max_batch_queries;  /* queries merged into one batch, and the largest request unless requests
+                                 are split (default 4096) */
   int64_t memory_budget;      /* device bytes that admitted requests may reserve (default 4 GiB) */
   int64_t pairs_per_query;    /* output pairs reserved per query (default 256) */
   int64_t max_pending;        /* requests held (queued, running or not yet polled) at most (default 4096) */
-  int32_t reserved[8];
+  int64_t split_queries;      /* > 0: a request of more rows is queued as pieces of at most this many rows,
+                                 which free slots take (and run side by side) like separate requests; the
+                                 request completes with its last piece, its result joined in row order;
+                                 at most max_batch_queries.  0 (default): every request is one piece */
+  int32_t reserved[6];
 } apss_server_opts;
 
 void apss_server_default_opts(apss_server_opts* opts);
@@ -275,7 +280,7 @@ int apss_server_create(apss_index* idx, const apss_server_opts* opts, apss_serve
  * CSR conventions above) with thresholds t_per_row[q] (host, may be NULL:
  * t for every row).  *req_id identifies it for apss_poll.  nq = 0 is a
  * request with an empty result.
- * Errors: APSS_EINVAL (bad CSR, nq > max_batch_queries), APSS_ETHRESH (a
+ * Errors: APSS_EINVAL (bad CSR, nq > max_batch_queries without split_queries), APSS_ETHRESH (a
  * threshold outside [t_build, 1]), APSS_EBUSY (not admitted now: retry),
  * APSS_ENOMEM (the request alone needs more than memory_budget). */
 int apss_submit(apss_server* srv, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col, const float* q_val,
@@ -311,7 +316,7 @@ typedef struct {
   int64_t rejected_busy;        /* submits refused with APSS_EBUSY */
   int64_t completed;            /* requests finished (including failed) */
   int64_t failed;               /* requests finished with an error */
-  int64_t queued;               /* requests waiting for a slot now */
+  int64_t queued;               /* request pieces waiting for a slot now */
   int64_t batches;              /* batches started */
   int64_t queries;              /* query rows in started batches */
   int64_t overlapped_batches;   /* batches started while another batch was running */

@@ -65,7 +65,8 @@ SERVER_MAX_SLOTS = 8
 class ServerOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("slots", ctypes.c_int32), ("max_batch_queries", ctypes.c_int64),
                 ("memory_budget", ctypes.c_int64), ("pairs_per_query", ctypes.c_int64),
-                ("max_pending", ctypes.c_int64), ("reserved", ctypes.c_int32 * 8)]
+                ("max_pending", ctypes.c_int64), ("split_queries", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class RequestInfo(ctypes.Structure):

@@ -1,14 +1,17 @@
 // Serving loop: continuous batching of query requests against a resident
 // index (Find-Matches, Algorithm 2, for many queries at once).
 //
-// Requests are validated and copied at submit, then wait in one FIFO.  Each
-// slot is a host thread with its own stream and workspace: whenever it is
-// free it takes every waiting request that fits its batch (at most
-// max_batch_queries queries, at least one request), concatenates them into
-// one query set with per-row thresholds, runs the query kernels on its
-// stream and splits the sorted pairs back into per-request results.  Slots
-// run independently, so a batch formed from requests that arrived while
-// another batch was on the GPU runs beside it.
+// Requests are validated and copied at submit, then wait in one FIFO as
+// chunks of consecutive rows (one chunk per request, or pieces of at most
+// split_queries rows).  Each slot is a host thread with its own stream and
+// workspace: whenever it is free it takes every waiting chunk that fits its
+// batch (at most max_batch_queries queries, at least one chunk),
+// concatenates them into one query set with per-row thresholds, runs the
+// query kernels on its stream and splits the sorted pairs back per chunk; a
+// request is complete when its last chunk is, and its pieces are joined in
+// row order.  Slots run independently, so a batch formed from requests that
+// arrived while another batch was on the GPU runs beside it, and the pieces
+// of a large request run on several slots at once.
 //
 // Admission: each request reserves the device bytes its staging and pair
 // buffers need (an estimate from its size, see request_bytes); submit
@@ -70,6 +73,17 @@ struct Request {
   int64_t batch = -1;
   int32_t batch_requests = 0;
   int32_t slot = -1;
+  // pieces of the request queued as separate chunks
+  int chunks = 1, chunks_done = 0;
+  bool started = false;
+  std::vector<apss_pairs> parts;
+};
+
+// Rows [q0, q1) of a request, queued as one unit of batching.
+struct Chunk {
+  Request* r = nullptr;
+  int64_t q0 = 0, q1 = 0;
+  int idx = 0;
 };
 
 void free_pairs(apss_pairs& p) {
@@ -86,7 +100,7 @@ struct apss_server {
   apss_server_opts o;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<Request*> queue;
+  std::deque<Chunk> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
   std::vector<std::thread> workers;
   bool stop = false;
@@ -126,8 +140,9 @@ int validate_request(const apss_index* ix, int64_t nq, const int64_t* rp, const 
     const int rc = check_t(ix, tq);
     if (rc) return rc;
     double sq = 0.0;
-    dims.assign(col + b, col + e);
+    bool increasing = true;  // ids in increasing order have no repeats
     for (int64_t k = b; k < e; ++k) {
+      if (k > b && col[k] <= col[k - 1]) increasing = false;
       if (col[k] < 0 || (int64_t)col[k] >= ix->m) {
         set_error("dimension id outside [0, m) (row %lld)", (long long)q);
         return APSS_EINVAL;
@@ -142,10 +157,13 @@ int validate_request(const apss_index* ix, int64_t nq, const int64_t* rp, const 
       set_error("non-empty rows must have unit L2 norm (|norm - 1| <= 1e-5) (row %lld)", (long long)q);
       return APSS_EINVAL;
     }
-    std::sort(dims.begin(), dims.end());
-    if (std::adjacent_find(dims.begin(), dims.end()) != dims.end()) {
-      set_error("repeated dimension id inside a row (row %lld)", (long long)q);
-      return APSS_EINVAL;
+    if (!increasing) {
+      dims.assign(col + b, col + e);
+      std::sort(dims.begin(), dims.end());
+      if (std::adjacent_find(dims.begin(), dims.end()) != dims.end()) {
+        set_error("repeated dimension id inside a row (row %lld)", (long long)q);
+        return APSS_EINVAL;
+      }
     }
   }
   return APSS_OK;
@@ -158,21 +176,26 @@ struct Staging {
   PinnedBuf<float> val, tq;
 };
 
-void run_batch(apss_server* S, Workspace& ws, RankRows& rows, Staging& hs, std::vector<Request*>& batch) {
+// A chunk's status and pairs (rows numbered within its request).
+void fail_chunk(const Chunk& c, int rc, const std::string& msg) {
+  if (!c.r->status) {
+    c.r->status = rc;
+    c.r->error = msg;
+  }
+}
+
+void run_batch(apss_server* S, Workspace& ws, RankRows& rows, Staging& hs, std::vector<Chunk>& batch) {
   apss_index* ix = S->ix;
   int64_t nq = 0, nnz = 0, cap = 0;
-  for (Request* r : batch) {
-    nq += r->nq;
-    nnz += r->nnz;
-    cap += S->o.pairs_per_query * r->nq;
+  for (const Chunk& c : batch) {
+    nq += c.q1 - c.q0;
+    nnz += c.r->rp[(size_t)c.q1] - c.r->rp[(size_t)c.q0];
+    cap += S->o.pairs_per_query * (c.q1 - c.q0);
   }
   std::vector<int64_t> row0(batch.size() + 1);
   if (!hs.rp.reserve((size_t)nq + 1) || !hs.col.reserve((size_t)nnz) || !hs.val.reserve((size_t)nnz) ||
       !hs.tq.reserve((size_t)nq)) {
-    for (Request* r : batch) {
-      r->status = APSS_ENOMEM;
-      r->error = "pinned host allocation failed";
-    }
+    for (const Chunk& c : batch) fail_chunk(c, APSS_ENOMEM, "pinned host allocation failed");
     return;
   }
   int64_t* const rp = hs.rp.p;
@@ -181,14 +204,16 @@ void run_batch(apss_server* S, Workspace& ws, RankRows& rows, Staging& hs, std::
   float* const tq = hs.tq.p;
   int64_t q0 = 0, k0 = 0;
   for (size_t b = 0; b < batch.size(); ++b) {
-    Request* r = batch[b];
+    const Chunk& c = batch[b];
+    const Request* r = c.r;
+    const int64_t kb = r->rp[(size_t)c.q0], ke = r->rp[(size_t)c.q1];
     row0[b] = q0;
-    for (int64_t q = 0; q < r->nq; ++q) rp[(size_t)(q0 + q)] = k0 + r->rp[(size_t)q];
-    std::copy(r->col.begin(), r->col.end(), col + k0);
-    std::copy(r->val.begin(), r->val.end(), val + k0);
-    std::copy(r->t.begin(), r->t.end(), tq + q0);
-    q0 += r->nq;
-    k0 += r->nnz;
+    for (int64_t q = c.q0; q < c.q1; ++q) rp[(size_t)(q0 + q - c.q0)] = k0 + r->rp[(size_t)q] - kb;
+    std::copy(r->col.begin() + kb, r->col.begin() + ke, col + k0);
+    std::copy(r->val.begin() + kb, r->val.begin() + ke, val + k0);
+    std::copy(r->t.begin() + c.q0, r->t.begin() + c.q1, tq + q0);
+    q0 += c.q1 - c.q0;
+    k0 += ke - kb;
   }
   row0[batch.size()] = q0;
   rp[(size_t)nq] = nnz;
@@ -205,13 +230,14 @@ void run_batch(apss_server* S, Workspace& ws, RankRows& rows, Staging& hs, std::
     if (!rc) rc = finish_host(ws, cnt, ceil_log2((uint64_t)ix->n), &all);
   }
   const std::string msg = rc ? last_error() : std::string();
-  // split the (query row, corpus row)-sorted pairs by request
+  // split the (query row, corpus row)-sorted pairs by chunk
   int64_t k = 0;
   for (size_t b = 0; b < batch.size(); ++b) {
-    Request* r = batch[b];
-    r->status = rc;
-    r->error = msg;
-    if (rc) continue;
+    const Chunk& ch = batch[b];
+    if (rc) {
+      fail_chunk(ch, rc, msg);
+      continue;
+    }
     const int64_t lo = k;
     while (k < all.count && (int64_t)all.i[k] < row0[b + 1]) ++k;
     const int64_t c = k - lo;
@@ -219,18 +245,51 @@ void run_batch(apss_server* S, Workspace& ws, RankRows& rows, Staging& hs, std::
     apss_pairs p{c, (uint32_t*)malloc(nbytes * 4), (uint32_t*)malloc(nbytes * 4), (float*)malloc(nbytes * 4)};
     if (!p.i || !p.j || !p.sim) {
       free_pairs(p);
-      r->status = APSS_ENOMEM;
-      r->error = "host allocation failed";
+      fail_chunk(ch, APSS_ENOMEM, "host allocation failed");
       continue;
     }
     for (int64_t x = 0; x < c; ++x) {
-      p.i[x] = (uint32_t)((int64_t)all.i[lo + x] - row0[b]);
+      p.i[x] = (uint32_t)((int64_t)all.i[lo + x] - row0[b] + ch.q0);
       p.j[x] = all.j[lo + x];
       p.sim[x] = all.sim[lo + x];
     }
-    r->pairs = p;
+    ch.r->parts[(size_t)ch.idx] = p;
   }
   free_pairs(all);
+}
+
+// The pieces of a request joined in row order into its result.
+void assemble(Request* r) {
+  if (r->status) {
+    for (apss_pairs& p : r->parts) free_pairs(p);
+    return;
+  }
+  if (r->parts.size() == 1) {
+    r->pairs = r->parts[0];
+    r->parts[0] = apss_pairs{0, nullptr, nullptr, nullptr};
+    return;
+  }
+  int64_t total = 0;
+  for (const apss_pairs& p : r->parts) total += p.count;
+  const size_t nbytes = (size_t)(total > 0 ? total : 1);
+  apss_pairs out{total, (uint32_t*)malloc(nbytes * 4), (uint32_t*)malloc(nbytes * 4), (float*)malloc(nbytes * 4)};
+  if (!out.i || !out.j || !out.sim) {
+    free_pairs(out);
+    r->status = APSS_ENOMEM;
+    r->error = "host allocation failed";
+  } else {
+    int64_t o = 0;
+    for (const apss_pairs& p : r->parts) {
+      if (p.count) {
+        memcpy(out.i + o, p.i, sizeof(uint32_t) * (size_t)p.count);
+        memcpy(out.j + o, p.j, sizeof(uint32_t) * (size_t)p.count);
+        memcpy(out.sim + o, p.sim, sizeof(float) * (size_t)p.count);
+      }
+      o += p.count;
+    }
+    r->pairs = out;
+  }
+  for (apss_pairs& p : r->parts) free_pairs(p);
 }
 
 void worker(apss_server* S, int slot) {
@@ -256,7 +315,7 @@ void worker(apss_server* S, int slot) {
   S->cv_done.notify_all();
   if (rc) return;
   for (;;) {
-    std::vector<Request*> batch;
+    std::vector<Chunk> batch;
     int64_t bid = 0;
     bool more = false;
     {
@@ -265,10 +324,10 @@ void worker(apss_server* S, int slot) {
       if (S->stop) break;
       int64_t q = 0;
       while (!S->queue.empty()) {
-        Request* r = S->queue.front();
-        if (!batch.empty() && q + r->nq > S->o.max_batch_queries) break;
-        batch.push_back(r);
-        q += r->nq;
+        const Chunk& c = S->queue.front();
+        if (!batch.empty() && q + (c.q1 - c.q0) > S->o.max_batch_queries) break;
+        batch.push_back(c);
+        q += c.q1 - c.q0;
         S->queue.pop_front();
       }
       bid = S->next_batch++;
@@ -278,7 +337,10 @@ void worker(apss_server* S, int slot) {
       ++S->st.batches;
       S->st.queries += q;
       const Clock::time_point now = Clock::now();
-      for (Request* r : batch) {
+      for (const Chunk& c : batch) {
+        Request* r = c.r;
+        if (r->started) continue;
+        r->started = true;
         r->t_start = now;
         r->batch = bid;
         r->batch_requests = (int32_t)batch.size();
@@ -304,19 +366,27 @@ void worker(apss_server* S, int slot) {
       ws.ss.v64a.release();
       ws.ss.v64b.release();
     }
+    // requests whose last chunk this batch held are joined and handed over
+    std::vector<Request*> finished;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (const Chunk& c : batch)
+        if (++c.r->chunks_done == c.r->chunks) finished.push_back(c.r);
+      S->st.regrows += ws.regrows - regrows0;
+      S->st.device_bytes[slot] = ws.bytes() + rows.rp.bytes() + rows.rc.bytes() + rows.mw.bytes();
+      --S->running;
+    }
+    for (Request* r : finished) assemble(r);
     {
       std::lock_guard<std::mutex> lk(S->mu);
       const Clock::time_point now = Clock::now();
-      for (Request* r : batch) {
+      for (Request* r : finished) {
         r->t_done = now;
         r->done = true;
         S->reserved -= r->bytes;
         ++S->st.completed;
         if (r->status) ++S->st.failed;
       }
-      S->st.regrows += ws.regrows - regrows0;
-      S->st.device_bytes[slot] = ws.bytes() + rows.rp.bytes() + rows.rc.bytes() + rows.mw.bytes();
-      --S->running;
     }
     S->cv_done.notify_all();
   }
@@ -339,6 +409,7 @@ void apss_server_default_opts(apss_server_opts* o) {
   o->memory_budget = 4ll << 30;
   o->pairs_per_query = 256;
   o->max_pending = 4096;
+  o->split_queries = 0;
 }
 
 int apss_server_create(apss_index* ix, const apss_server_opts* opts, apss_server** out) {
@@ -357,7 +428,8 @@ int apss_server_create(apss_index* ix, const apss_server_opts* opts, apss_server
     o = *opts;
   }
   if (o.slots < 1 || o.slots > APSS_SERVER_MAX_SLOTS || o.max_batch_queries < 1 ||
-      o.max_batch_queries >= (1ll << 31) || o.memory_budget < 1 || o.pairs_per_query < 0 || o.max_pending < 1) {
+      o.max_batch_queries >= (1ll << 31) || o.memory_budget < 1 || o.pairs_per_query < 0 || o.max_pending < 1 ||
+      o.split_queries < 0 || o.split_queries > o.max_batch_queries) {
     set_error("server options out of range");
     return APSS_EINVAL;
   }
@@ -417,7 +489,8 @@ int apss_submit(apss_server* S, int64_t nq, const int64_t* q_row_ptr, const int3
     set_error("row_ptr[nq] must be in [0, 2^32), with col and val given");
     return APSS_EINVAL;
   }
-  if (nq > S->o.max_batch_queries) {
+  // a request is batched whole unless it is split into pieces, which then fit a batch
+  if (S->o.split_queries == 0 && nq > S->o.max_batch_queries) {
     set_error("request of %lld queries exceeds max_batch_queries %lld", (long long)nq,
               (long long)S->o.max_batch_queries);
     return APSS_EINVAL;
@@ -458,10 +531,21 @@ int apss_submit(apss_server* S, int64_t nq, const int64_t* q_row_ptr, const int3
     S->st.peak_reserved_bytes = std::max(S->st.peak_reserved_bytes, S->reserved);
     ++S->st.submitted;
     *req_id = r->id;
-    S->queue.push_back(r.get());
+    // pieces of at most split_queries rows (one piece when 0 or larger)
+    const int64_t piece = (S->o.split_queries > 0 && nq > S->o.split_queries) ? S->o.split_queries : std::max<int64_t>(nq, 1);
+    r->chunks = (int)((std::max<int64_t>(nq, 1) + piece - 1) / piece);
+    r->parts.assign((size_t)r->chunks, apss_pairs{0, nullptr, nullptr, nullptr});
+    for (int c = 0; c < r->chunks; ++c) {
+      Chunk ch;
+      ch.r = r.get();
+      ch.q0 = std::min<int64_t>(nq, (int64_t)c * piece);
+      ch.q1 = std::min<int64_t>(nq, (int64_t)(c + 1) * piece);
+      ch.idx = c;
+      S->queue.push_back(ch);
+    }
     S->reqs.emplace(r->id, std::move(r));
   }
-  S->cv_work.notify_one();
+  S->cv_work.notify_all();
   return APSS_OK;
 }
 
@@ -542,7 +626,10 @@ void apss_server_destroy(apss_server* S) {
   }
   S->cv_work.notify_all();
   for (auto& w : S->workers) w.join();
-  for (auto& kv : S->reqs) free_pairs(kv.second->pairs);
+  for (auto& kv : S->reqs) {
+    free_pairs(kv.second->pairs);
+    for (apss_pairs& p : kv.second->parts) free_pairs(p);
+  }
   delete S;
 }
 

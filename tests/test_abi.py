@@ -80,9 +80,11 @@ int main(void) {
   printf("apss_server_counters %zu\n", sizeof(apss_server_counters));
   printf("apss_tune_result %zu\n", sizeof(apss_tune_result));
   F(apss_opts, stream) F(apss_opts, query_safe) F(apss_opts, variant) F(apss_opts, head_dims)
-  F(apss_opts, range_rows) F(apss_opts, screen_dims) F(apss_opts, graph) F(apss_opts, reserved)
+  F(apss_opts, range_rows) F(apss_opts, screen_dims) F(apss_opts, graph) F(apss_opts, index_all)
+  F(apss_opts, local_parts) F(apss_opts, remscore) F(apss_opts, reserved)
   F(apss_server_opts, slots) F(apss_server_opts, max_batch_queries) F(apss_server_opts, memory_budget)
-  F(apss_server_opts, pairs_per_query) F(apss_server_opts, max_pending) F(apss_server_opts, reserved)
+  F(apss_server_opts, pairs_per_query) F(apss_server_opts, max_pending) F(apss_server_opts, split_queries)
+  F(apss_server_opts, reserved)
   F(apss_request_info, latency_ms) F(apss_request_info, batch) F(apss_request_info, batch_requests)
   F(apss_request_info, slot)
   F(apss_server_counters, running) F(apss_server_counters, submitted) F(apss_server_counters, peak_reserved_bytes)

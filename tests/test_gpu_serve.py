@@ -218,7 +218,7 @@ def test_regrown_slot_buffers_are_released(apss):
     from synth.corpus import from_rows
     base = make_corpus(spec_for("c1", n=1))
     row = dict(zip(base.row(0)[0].tolist(), base.row(0)[1].tolist()))
-    other = make_corpus(spec_for("c1", n=2000))
+    other = make_corpus(spec_for("c1", n=2000, seed=77))
     rows = [row] * 3000 + [dict(zip(*[a.tolist() for a in other.row(k)])) for k in range(other.n)]
     V = from_rows(rows, base.m)
     Q = from_rows([row] * 40, base.m)            # 40 x 3000 = 120,000 pairs
@@ -237,3 +237,29 @@ def test_regrown_slot_buffers_are_released(apss):
     assert st["device_bytes"][0] < 12 * 120000
     assert len(small[0]) == 3000 and st2["failed"] == 0
     assert_parity(i, j, s, oracle.query(V, Q, t=0.9), 0.9, Q, V)
+
+
+def test_split_requests_equal_whole_requests(apss, corpus, index):
+    """Requests queued as pieces of at most 7 rows, run by two slots side by
+    side, give each request the same pairs, bit for bit, as whole requests."""
+    V, Q = corpus
+    reqs = split_requests(Q, seed=11)[:40]
+    whole, pieces = [], []
+    with apss.Server(index, slots=1) as srv:
+        for lo, hi, t in reqs:
+            whole.append(srv.poll(srv.submit(rows_of(Q, lo, hi), t_per_row=t))[:3])
+    with apss.Server(index, slots=2, split_queries=7, max_batch_queries=16) as srv:
+        ids = [srv.submit(rows_of(Q, lo, hi), t_per_row=t) for lo, hi, t in reqs]
+        for rid in ids:
+            pieces.append(srv.poll(rid)[:3])
+        st = srv.stats()
+    assert st["failed"] == 0 and st["completed"] == len(reqs)
+    assert st["batches"] >= sum((hi - lo + 6) // 7 for lo, hi, _ in reqs) // 3
+    for (ai, aj, as_), (bi, bj, bs) in zip(whole, pieces):
+        assert np.array_equal(ai, bi) and np.array_equal(aj, bj)
+        assert np.array_equal(as_.view(np.uint32), bs.view(np.uint32))
+    lo, hi, t = max(reqs, key=lambda r: r[1] - r[0])
+    R = rows_of(Q, lo, hi)
+    k = reqs.index((lo, hi, t))
+    assert_parity(*pieces[k], oracle.query(V, R, t_per_row=t.astype(np.float64)), None, R, V,
+                  per_row_t=t.astype(np.float64))
