@@ -282,6 +282,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     sm.ovf = 0;
     sm.vtot = 0;
   }
+  if (tid < QT) sm.qhead[tid] = 0;  // staged tiles count their dense-table components
   for (int e = tid; e < QT * RD; e += NT) sm.qd[e] = 0.0f;
   __syncthreads();
   const int64_t qbase = uni64(sm.qoff[0]);
@@ -378,7 +379,12 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       const int qi = cq[j];
       bool admits = true;  // remscore: the component admits new candidates
       if constexpr (REM) admits = valid && qbase + k - sm.qoff[qi] >= (int64_t)a.qadm[q0 + qi];
-      if (valid && c.r < RD) sm.qd[qi * RD + c.r] = c.w;
+      if (valid && c.r < RD) {
+        // rows are in rank order: a query's components of rank < RD come
+        // first, and their count is the position of its first other one
+        sm.qd[qi * RD + c.r] = c.w;
+        atomicAdd(&sm.qhead[qi], 1);
+      }
       // no list entry in the item's corpus range, or a rank outside the item's part
       const bool dead = !valid || p1[j] == p0[j] || c.r < plo || c.r >= phi;
       vmine += dead ? 0 : (int32_t)(p1[j] - p0[j]);
@@ -433,20 +439,24 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   for (int o = 32; o >= 1; o >>= 1) vmine += __shfl_xor(vmine, o, 64);
   if (lane == 0 && vmine) atomicAdd(&sm.vtot, vmine);
   __syncthreads();
-  if (staged && tid < qn) sm.qhead[tid] = find_head(sm.qrow + (sm.qoff[tid] - qbase), sm.qlen[tid]);
-  if (tid == 0) {
+  if (wave == 0) {
     // a slot's L2 bound A + qb.w * pnrm >= qb.x implies the row test
     // amax + rtest.y * pnrm >= rtest.x for the row's largest score amax
     // (float sums and products are monotone; the 4,096 units, 4e-6 of a
-    // score, cover a fused multiply-add on one side only)
+    // score, cover a fused multiply-add on one side only).  Read by the
+    // filters, after barriers to come.
     float tmin = 3.0e38f, wmax = 0.0f;
-    for (int qi = 0; qi < qn; ++qi) {
-      tmin = fminf(tmin, sm.qb[qi].x);
-      wmax = fmaxf(wmax, sm.qb[qi].w);
+    if (lane < qn) {
+      tmin = sm.qb[lane].x;
+      wmax = sm.qb[lane].w;
     }
-    sm.rtest = make_float2(tmin - 4096.0f, wmax);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      tmin = fminf(tmin, __shfl_xor(tmin, o, 64));
+      wmax = fmaxf(wmax, __shfl_xor(wmax, o, 64));
+    }
+    if (lane == 0) sm.rtest = make_float2(tmin - 4096.0f, wmax);
   }
-  __syncthreads();
 
   // q[r] for the query in slot qi (0 if absent)
   auto qlookup = [&](int qi, int32_t r) -> float {
