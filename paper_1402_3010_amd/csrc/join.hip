@@ -629,10 +629,12 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       else sm.sq[e].y = 0u;
     }
     __syncthreads();
-    // rescore: one wave per verified pair
+    // rescore: one wave per verified pair; each wave's kept pairs are
+    // written together
     for (int base = wave * 64; base < ns; base += NT) {
       const int e = base + lane;
       uint64_t fm = __ballot(e < ns && sm.sq[e < ns ? e : 0].y != 0u);
+      WaveEmit em;
       while (fm) {
         const int l = __ffsll((unsigned long long)fm) - 1;
         fm &= fm - 1;
@@ -649,16 +651,12 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         bool banded;
         const bool keep = wave_decide(yrow, ylen, lane, look, s32, sm.qt[qi], &sim, &banded);
         if (banded && lane == 0) ++c_band;
-        if (keep && lane == 0) {
+        if (keep) {
           const uint64_t qid = (uint64_t)(q0 + qi);
-          const uint64_t key = a.triangle ? (((uint64_t)y << a.bj) | qid) : ((qid << a.bj) | (uint64_t)y);
-          const unsigned long long idx = atomicAdd(&a.counters[C_MATCHES], 1ull);
-          if ((int64_t)idx < a.cap) {
-            a.out_key[idx] = key;
-            a.out_sim[idx] = sim;
-          }
+          em.add(lane, a.triangle ? (((uint64_t)y << a.bj) | qid) : ((qid << a.bj) | (uint64_t)y), sim);
         }
       }
+      em.flush(lane, a.counters, a.out_key, a.out_sim, a.cap);
     }
     __syncthreads();
     if (tid == 0) {

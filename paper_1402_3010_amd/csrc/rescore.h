@@ -79,4 +79,36 @@ __device__ __forceinline__ bool wave_decide(const RComp* __restrict__ y, int yle
   return s32 >= tq;
 }
 
+// Pair compaction of one wavefront: the wave's kept pairs wait in its lanes
+// (the k-th in lane k) and are written at consecutive output positions
+// reserved by one counter atomic per flush, at most 64 pairs at a time.
+// add() and flush() are called by every lane of the wave with the same
+// arguments (the decisions above are wave-uniform).  The counter still
+// counts pairs past the capacity, whose writes are dropped.
+struct WaveEmit {
+  uint64_t key = 0;
+  float sim = 0.0f;
+  int n = 0;  // pairs held; wave-uniform, at most 64
+  __device__ __forceinline__ void add(int lane, uint64_t k, float s) {
+    if (lane == n) {
+      key = k;
+      sim = s;
+    }
+    ++n;
+  }
+  __device__ __forceinline__ void flush(int lane, unsigned long long* counters, uint64_t* __restrict__ out_key,
+                                        float* __restrict__ out_sim, int64_t cap) {
+    if (n == 0) return;
+    unsigned long long b = 0;
+    if (lane == 0) b = atomicAdd(&counters[C_MATCHES], (unsigned long long)n);
+    b = (unsigned long long)__shfl((long long)b, 0, 64);
+    const int64_t k = (int64_t)b + lane;
+    if (lane < n && k < cap) {
+      out_key[k] = key;
+      out_sim[k] = sim;
+    }
+    n = 0;
+  }
+};
+
 }  // namespace apss

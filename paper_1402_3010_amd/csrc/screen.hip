@@ -278,6 +278,7 @@ __global__ __launch_bounds__(256) void k_screen_verify(const uint64_t* __restric
   const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const uint64_t jmask = (1ull << bj) - 1ull;
+  WaveEmit em;
   for (int64_t p = wv; p < nc; p += nw) {
     const uint64_t key = cand[p];
     const int64_t i = (int64_t)(key >> bj), j = (int64_t)(key & jmask);
@@ -297,17 +298,13 @@ __global__ __launch_bounds__(256) void k_screen_verify(const uint64_t* __restric
     float sim;
     bool banded;
     const bool keep = wave_decide(yrow, ylen, lane, look, s32, t, &sim, &banded);
-    if (lane == 0) {
-      if (banded) atomicAdd(&counters[C_BAND], 1ull);
-      if (keep) {
-        const unsigned long long k = atomicAdd(&counters[C_MATCHES], 1ull);
-        if ((int64_t)k < cap) {
-          out_key[k] = key;
-          out_sim[k] = sim;
-        }
-      }
+    if (banded && lane == 0) atomicAdd(&counters[C_BAND], 1ull);
+    if (keep) {
+      em.add(lane, key, sim);
+      if (em.n == 64) em.flush(lane, counters, out_key, out_sim, cap);
     }
   }
+  em.flush(lane, counters, out_key, out_sim, cap);
 }
 
 }  // namespace
