@@ -92,7 +92,10 @@ typedef struct {
                             processed, the current one included, is below t; a candidate all of
                             whose indexed overlap lies in components past that point is dropped
                             before the bounds.  0 (default): off */
-  int32_t reserved[5];
+  int32_t range_group;   /* corpus ranges per work item of the join (1 to 64): an item stages its
+                            query tile once and visits that many consecutive ranges in turn;
+                            0 = 1.  The environment variable APSS_RANGE_GROUP overrides it. */
+  int32_t reserved[4];
 } apss_opts;
 
 void apss_default_opts(apss_opts* opts);
@@ -206,6 +209,7 @@ const char* apss_last_error(void);
  * Times the join kernel at threshold t on this index under every compiled
  * tile variant (queries per tile x corpus rows per LDS accumulator block)
  * and several corpus-range widths of the persistent kernel's work items,
+ * then, for the fastest of those, several numbers of ranges per work item,
  * and keeps the fastest for later joins on the index (for an index built
  * with screen_dims > 0: the sparse pass of the screened join).  budget_ms > 0
  * stops trying further configurations once that much host time has passed
@@ -216,12 +220,13 @@ const char* apss_last_error(void);
  * tuning.  The index must not be in use by another call or a server. */
 typedef struct {
   int32_t variant;             /* chosen tile variant */
-  int32_t range_rows;          /* chosen corpus rows per work item */
+  int32_t range_rows;          /* chosen corpus rows per work-item range */
   double ms;                   /* its join kernel time (from the cache if from_cache) */
   int32_t from_cache;          /* 1: taken from the cache file without timing */
   int32_t tried;               /* configurations timed */
   int32_t cache_write_failed;  /* 1: the cache file could not be written */
-  int32_t reserved[3];
+  int32_t range_group;         /* chosen ranges per work item */
+  int32_t reserved[2];
 } apss_tune_result;
 
 int apss_autotune(apss_index* idx, float t, double budget_ms, const char* cache_path, apss_tune_result* out);

@@ -42,8 +42,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("stream", ctypes.c_void_p), ("query_safe", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("head_dims", ctypes.c_int32), ("range_rows", ctypes.c_int32),
                 ("screen_dims", ctypes.c_int32), ("graph", ctypes.c_int32), ("index_all", ctypes.c_int32),
-                ("local_parts", ctypes.c_int32), ("remscore", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("local_parts", ctypes.c_int32), ("remscore", ctypes.c_int32), ("range_group", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Pairs(ctypes.Structure):
@@ -84,7 +84,7 @@ class ServerCounters(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("range_rows", ctypes.c_int32), ("ms", ctypes.c_double),
                 ("from_cache", ctypes.c_int32), ("tried", ctypes.c_int32), ("cache_write_failed", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("range_group", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 _LIB = None
@@ -209,7 +209,7 @@ def current_stream_handle() -> Optional[int]:
 
 def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, variant: int = -1,
                  range_rows: int = 0, screen_dims: int = 0, graph: bool = False, index_all: bool = False,
-                 local_parts: int = 0, remscore: bool = False) -> Opts:
+                 local_parts: int = 0, remscore: bool = False, range_group: int = 0) -> Opts:
     o = Opts()
     load().apss_default_opts(ctypes.byref(o))
     o.stream = stream
@@ -222,6 +222,7 @@ def default_opts(stream=None, query_safe: bool = True, head_dims: int = 0, varia
     o.index_all = 1 if index_all else 0
     o.local_parts = local_parts
     o.remscore = 1 if remscore else 0
+    o.range_group = range_group
     return o
 
 
@@ -369,7 +370,7 @@ class Index:
     def build(cls, V, t_build: float, stream=None, query_safe: bool = True, head_dims: int = 0,
               on_device: bool = False, variant: int = -1, range_rows: int = 0, screen_dims: int = 0,
               graph: bool = False, index_all: bool = False, local_parts: int = 0,
-              remscore: bool = False) -> "Index":
+              remscore: bool = False, range_group: int = 0) -> "Index":
         """V: object with n, m, row_ptr, col, val (numpy), or a tuple (n, m, row_ptr, col, val) of tensors."""
         if isinstance(V, tuple):
             n, m, rp, col, val = V
@@ -384,7 +385,7 @@ class Index:
             stream = current_stream_handle()
         h = build_index(n, m, rp, col, val, t_build, default_opts(stream, query_safe, head_dims, variant, range_rows,
                                                                       screen_dims, graph, index_all, local_parts,
-                                                                      remscore))
+                                                                      remscore, range_group))
         return cls(h, int(n), int(m))
 
     def join(self, t: float):

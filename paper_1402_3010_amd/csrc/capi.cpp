@@ -375,6 +375,7 @@ int build_screen(apss_index* ix, int32_t head) {
   sx->t_build = ix->t_build;
   sx->variant = ix->variant;
   sx->range_rows = ix->range_rows;
+  sx->range_group = ix->range_group;
   sx->head_cut = head;
   sx->rows.n = ix->rows.n;
   sx->rows.nnz = ix->rows.nnz;
@@ -466,18 +467,21 @@ int plan_layout(apss_index* ix, const QuerySet& Q, int triangle, JoinLayout& L) 
   const int64_t range_rows = ix->toff_rows;
   L.K = (int)(range_rows / L.CB);
   L.nR = ix->toff_nR;
+  L.rg = std::max(1, std::min<int>(ix->range_group, kMaxRangeGroup));
   L.tiles = make_tiles(Q.rp_host, Q.n, L.QT, join_variant_staging(variant));
   L.ntiles = (int64_t)L.tiles.start.size() - 1;
-  L.nrx = (L.nR + 7) / 8;
+  const int64_t ngroups = (L.nR + L.rg - 1) / L.rg;
+  L.nrx = (ngroups + 7) / 8;
   L.parts = ix->parts;
   L.cum.assign((size_t)(8 * (L.nrx + 1)), 0);
   for (int x = 0; x < 8; ++x) {
     int64_t c = 0;
     for (int64_t j = 0; j <= L.nrx; ++j) {
       L.cum[(size_t)(x * (L.nrx + 1) + j)] = c;
-      const int64_t R = x + 8 * j;
-      if (j < L.nrx && R < L.nR) {
-        // first tile whose last query reaches the range (self-join triangle)
+      const int64_t g = x + 8 * j;
+      const int64_t R = g * L.rg;  // the group's first range
+      if (j < L.nrx && g < ngroups) {
+        // first tile whose last query reaches the group's first range (self-join triangle)
         const int64_t tmin =
             triangle ? (int64_t)(std::upper_bound(L.tiles.start.begin() + 1, L.tiles.start.end(), R * range_rows) -
                                  (L.tiles.start.begin() + 1))
@@ -526,6 +530,8 @@ void bind_plan(apss_index* ix, const QuerySet& Q, int triangle, float t, const f
   a.toff = ix->toff.p;
   a.m_tail = (int32_t)(ix->m - ix->H);
   a.K = L.K;
+  a.rg = L.rg;
+  a.nR = (int32_t)L.nR;
   a.nrx = L.nrx;
   a.qcum = qcum_dev;
   a.qctr = qctr_dev;
@@ -832,7 +838,8 @@ int64_t join_cap_hint(const apss_index* ix) { return std::max<int64_t>(1 << 20, 
 std::vector<const void*> graph_buffers(const apss_index* ix, const Workspace& ws) {
   return {ws.tstart.p, ws.qcum.p, ws.qctr.p, ws.counters.p, ws.wg_cur.p, ws.raw_key.p, ws.raw_sim.p, ws.ss.k2.p,
           ws.ss.v32b.p, ws.ss.hist.p, ws.ss.scan.p, ix->toff.p, ix->hoff[0].p, ix->hoff[1].p,
-          (const void*)(intptr_t)ix->variant, (const void*)(intptr_t)ix->range_rows};
+          (const void*)(intptr_t)ix->variant, (const void*)(intptr_t)ix->range_rows,
+          (const void*)(intptr_t)ix->range_group};
 }
 
 // Capture the launch sequence of the self-join that just ran (count pairs).
@@ -1178,6 +1185,10 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
     set_error("range_rows must be >= 0");
     return APSS_EINVAL;
   }
+  if (o.range_group < 0 || o.range_group > kMaxRangeGroup) {
+    set_error("range_group must be in [0, %d]", kMaxRangeGroup);
+    return APSS_EINVAL;
+  }
   if (o.screen_dims < 0 || o.screen_dims > kScreenMaxHead) {
     set_error("screen_dims must be in [0, %d]", kScreenMaxHead);
     return APSS_EINVAL;
@@ -1213,6 +1224,11 @@ int apss_build_index(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t
   if (const char* ev = getenv("APSS_RANGE_ROWS")) {
     const long long rr = atoll(ev);
     if (rr > 0) ix->range_rows = rr;
+  }
+  ix->range_group = o.range_group > 0 ? o.range_group : 1;
+  if (const char* ev = getenv("APSS_RANGE_GROUP")) {
+    const int g = atoi(ev);
+    if (g >= 1 && g <= kMaxRangeGroup) ix->range_group = g;
   }
   (void)hipGetDevice(&ix->device);
   if (o.screen_dims > 0 && !screen_variant_ok(ix->variant)) {

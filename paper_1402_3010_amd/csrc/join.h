@@ -36,12 +36,15 @@ struct JoinArgs {
   int32_t triangle;       // 1: self-join, query q only meets corpus rows y < q
   int64_t ntiles;
   const int64_t* tstart;  // [ntiles+1] first query of each tile (tiles hold <= QT queries)
-  // work items (corpus range of K blocks, query tile), queued per XCD
+  // work items (group of rg consecutive corpus ranges of K blocks each,
+  // query tile), queued per XCD
   const uint32_t* toff;   // [(nR+1) * m_tail] first entry of sparse list H + rt at or after range R
   int32_t m_tail;         // m - H
   int32_t K;              // blocks per range
-  int64_t nrx;            // range slots per XCD queue
-  const int64_t* qcum;    // [8 * (nrx+1)] cumulative item counts of queue x's ranges x, x+8, ...
+  int32_t rg;             // ranges per item (>= 1)
+  int32_t nR;             // corpus ranges
+  int64_t nrx;            // group slots per XCD queue
+  const int64_t* qcum;    // [8 * (nrx+1)] cumulative item counts of queue x's groups x, x+8, ...
   unsigned int* qctr;     // [8] next item of each queue (zero at launch)
   uint32_t* wg_cur;       // per-workgroup cursors of tiles too large to stage in LDS
   int64_t wg_cur_stride;  // 2 * largest tile's component count

@@ -222,10 +222,11 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     atomicOr(&sm.adm[b >> 5], 1u << (b & 31u));
   };
 
-  // Persistent loop over work items (corpus range R, query tile T).  The
-  // queue of XCD x holds the ranges R = x, x + 8, ... in order, so the
-  // workgroups resident on one XCD share one range of lists in its L2;
-  // an XCD whose queue is empty takes items from the others.
+  // Persistent loop over work items (group of rg consecutive corpus ranges,
+  // query tile T).  The queue of XCD x holds the groups x, x + 8, ... in
+  // order, so the workgroups resident on one XCD share a few ranges of lists
+  // in its L2; an XCD whose queue is empty takes items from the others.
+  // An item stages its tile once and then visits its ranges in turn.
   const int xcd = (int)(blockIdx.x & 7u);
   for (int qx = 0; qx < 8; ++qx) {
     const int x = (xcd + qx) & 7;
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       }
       __syncthreads();
       const int lo_j = uni(sm.slot);
-      const int64_t R = (int64_t)x + 8 * (int64_t)lo_j;
+      const int64_t grp = (int64_t)x + 8 * (int64_t)lo_j;  // range group
       int64_t u = it - cum[lo_j];
       // local pruning: consecutive items of a (range, tile) score its parts
       int32_t plo = 0, phi = 0x7FFFFFFF;
@@ -266,7 +267,6 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         phi = a.part_lo[pr + 1];
       }
       const int64_t tile = a.ntiles - 1 - u;
-      const int64_t b_begin = R * a.K;
   const int64_t q0 = a.tstart[tile];
   const int qn = (int)(a.tstart[tile + 1] - q0);
 
@@ -330,28 +330,74 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   };
   int64_t last_b = -1;
   if (qn > 0 && a.n > 0) last_b = a.triangle ? (q0 + qn - 1) / CB : (a.nb - 1);
-  const int64_t b_end = (b_begin + a.K) < (last_b + 1) ? (b_begin + a.K) : (last_b + 1);
   uint32_t* const gcur = a.wg_cur + (int64_t)blockIdx.x * a.wg_cur_stride;  // cursors of unstaged tiles
+  // the item's ranges: those of its group that hold rows the tile meets
+  // (the first always does: items exist only for such tiles)
+  const int64_t R0 = grp * a.rg;
+  int64_t R1 = R0 + a.rg - 1;
+  if (R1 > a.nR - 1) R1 = a.nR - 1;
+  if (last_b >= 0 && last_b / a.K < R1) R1 = last_b / a.K;
+  if (R1 < R0) R1 = R0;
 
-  // stage the tile, fill the dense lookup table, place every list cursor at
-  // the range's first block (block offsets for dense lists, range offsets
-  // for sparse ones), and fetch that block's segment ends of the dense lists
-  uint32_t hn[KMAX];
-#pragma unroll
-  for (int j = 0; j < KMAX; ++j) hn[j] = 0;
-  int32_t vmine = 0;  // this thread's share of the item's list entries
-  if (b_begin < b_end && staged) {
-    // A staged tile has at most QB = KMAX * NT components: every component
-    // load is issued first, then every list-offset load, then the LDS
-    // writes, so the loads' latencies overlap instead of adding up per
-    // component.  Live segments take their places by one atomic per wave.
-    RComp cc[KMAX];
-    int cq[KMAX];
+  // stage the tile once: its components, their query slots and admission
+  // flags, and the dense lookup table (each thread later reads back only the
+  // components it wrote, so no barrier is needed before the ranges)
+  if (staged && last_b >= R0 * a.K) {
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) {
       const int k = j * NT + tid;
-      cc[j] = k < tile_nnz ? a.qrc[qbase + k] : RComp{0x7FFFFFFF, 0.0f};
-      cq[j] = k < tile_nnz ? find_slot(qbase + k) : 0;
+      if (k < tile_nnz) {
+        const RComp c = a.qrc[qbase + k];
+        const int qi = find_slot(qbase + k);
+        bool admits = true;  // remscore: the component admits new candidates
+        if constexpr (REM) admits = qbase + k - sm.qoff[qi] >= (int64_t)a.qadm[q0 + qi];
+        if (c.r < RD) {
+          // rows are in rank order: a query's components of rank < RD come
+          // first, and their count is the position of its first other one
+          sm.qd[qi * RD + c.r] = c.w;
+          atomicAdd(&sm.qhead[qi], 1);
+        }
+        sm.qrow[k] = c;
+        sm.cqi[k] = (uint8_t)(qi | (admits ? 0x80 : 0));
+      }
+    }
+  }
+
+  for (int64_t R = R0; R <= R1; ++R) {
+  if (R > R0) {
+    // the previous range is done with the per-range fields
+    __syncthreads();
+    if (tid == 0) {
+      sm.nshort = 0;
+      sm.vtot = 0;
+    }
+    __syncthreads();
+  }
+  const int64_t b_begin = R * a.K;
+  const int64_t b_end = (b_begin + a.K) < (last_b + 1) ? (b_begin + a.K) : (last_b + 1);
+
+  // place every list cursor at the range's first block (block offsets for
+  // dense lists, range offsets for sparse ones), and fetch that block's
+  // segment ends of the dense lists
+  uint32_t hn[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) hn[j] = 0;
+  int32_t vmine = 0;  // this thread's share of the range's list entries
+  if (b_begin < b_end && staged) {
+    // A staged tile has at most QB = KMAX * NT components: every list-offset
+    // load is issued first, then the LDS writes, so the loads' latencies
+    // overlap instead of adding up per component.  Live segments take their
+    // places by one atomic per wave.
+    RComp cc[KMAX];
+    int cq[KMAX];
+    bool cadm[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      const int k = j * NT + tid;  // < QB: the LDS reads stay in bounds
+      const int c8 = sm.cqi[k];
+      cc[j] = k < tile_nnz ? sm.qrow[k] : RComp{0x7FFFFFFF, 0.0f};
+      cq[j] = c8 & 0x7F;
+      cadm[j] = (c8 >> 7) != 0;
     }
     uint32_t p0[KMAX], p1[KMAX];
 #pragma unroll
@@ -377,22 +423,13 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       const bool valid = k < tile_nnz;
       const RComp c = cc[j];
       const int qi = cq[j];
-      bool admits = true;  // remscore: the component admits new candidates
-      if constexpr (REM) admits = valid && qbase + k - sm.qoff[qi] >= (int64_t)a.qadm[q0 + qi];
-      if (valid && c.r < RD) {
-        // rows are in rank order: a query's components of rank < RD come
-        // first, and their count is the position of its first other one
-        sm.qd[qi * RD + c.r] = c.w;
-        atomicAdd(&sm.qhead[qi], 1);
-      }
-      // no list entry in the item's corpus range, or a rank outside the item's part
+      const bool admits = valid && cadm[j];
+      // no list entry in the corpus range, or a rank outside the item's part
       const bool dead = !valid || p1[j] == p0[j] || c.r < plo || c.r >= phi;
       vmine += dead ? 0 : (int32_t)(p1[j] - p0[j]);
       if (valid) {
-        sm.qrow[k] = c;
-        sm.cqi[k] = (uint8_t)(qi | (admits ? 0x80 : 0));
         // the block path loads the first entry's vector id of a sparse list
-        // once the item is known to take that path
+        // once the range is known to take that path
         sm.cur[k] = make_uint2(dead ? kDead : p0[j], 0u);
       }
       if (dead) hn[j] = 0u;
@@ -1278,6 +1315,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     }
   }
 
+  }  // ranges of the item
       if (tid == 0) sm.item = (int64_t)next_item;
     }  // items of queue x
   }    // queues

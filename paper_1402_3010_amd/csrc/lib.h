@@ -167,6 +167,7 @@ struct apss_index {
   float pnrm_max = 0.0f;    // largest unindexed-part norm over the rows (RowStat.pnrm)
   int variant = 1;          // tile variant of the join kernel
   int64_t range_rows = 0;   // corpus rows per work-item range
+  int32_t range_group = 1;  // ranges per work item
   int32_t head_cut = 0;     // > 0: the unindexed part of every row is its components of rank < head_cut
   apss_index* screen = nullptr;  // head-cut index over the same rows (screened join), owned
   apss::RankRows rows;  // corpus rows in rank space (densest dimension first)
@@ -210,7 +211,7 @@ struct Tiles {
 // Host side of one join kernel launch: geometry, query tiles and the
 // cumulative item counts of the 8 per-XCD work queues.
 struct JoinLayout {
-  int variant = 0, QT = 0, CB = 0, slot = 0, K = 0, G = 0, parts = 1;
+  int variant = 0, QT = 0, CB = 0, slot = 0, K = 0, G = 0, parts = 1, rg = 1;
   int64_t nb = 0, nR = 0, nrx = 0, ntiles = 0, wg_stride = 0;
   Tiles tiles;
   std::vector<int64_t> cum;  // 8 * (nrx + 1)
@@ -242,6 +243,8 @@ int check_t(const apss_index* ix, float t);
 // stream s, finished before return); safe to call from several threads.
 // Rebuilding the range table for another width while a join runs is not.
 int prepare(apss_index* ix, hipStream_t s, int variant, int64_t range_rows);
+// most corpus ranges one work item of the join visits
+constexpr int kMaxRangeGroup = 64;
 int64_t default_range_rows(int variant);
 // Query rows -> rank space on ws's stream (validates; t_per_row is host memory or NULL).
 int stage_queries(apss_index* ix, Workspace& ws, int64_t nq, const int64_t* q_row_ptr, const int32_t* q_col,

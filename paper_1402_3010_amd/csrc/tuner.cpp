@@ -1,12 +1,13 @@
 // Autotuner of the self-join: picks the compiled tile variant (queries per
-// tile x corpus rows per accumulator block) and the width of the corpus
-// ranges that form the persistent kernel's work items, by timing the join
-// kernel on the index itself, and remembers the choice in a small JSON file
-// keyed by device architecture and workload class.
+// tile x corpus rows per accumulator block), the width of the corpus ranges
+// and the number of ranges that one of the persistent kernel's work items
+// visits, by timing the join kernel on the index itself, and remembers the
+// choice in a small JSON file keyed by device architecture and workload class.
 //
 // Cache file: one JSON object with one entry per line,
-//   "gfx950|join|n=2^20|m=2^20|nnz=2^7|t=0.70": {"variant": 1, "range_rows": 8192, "ms": 3741.5},
-// written whole (temporary file + rename) after each tuning.
+//   "gfx950|join|n=2^20|m=2^20|nnz=2^7|t=0.70": {"variant": 1, "range_rows": 8192, "range_group": 1, "ms": 3741.5},
+// written whole (temporary file + rename) after each tuning; entries without
+// "range_group" mean 1.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -26,6 +27,7 @@ namespace {
 struct Choice {
   int variant = 1;
   long long range_rows = 8192;
+  int range_group = 1;
   double ms = 0.0;
 };
 
@@ -67,7 +69,9 @@ std::map<std::string, Choice> read_cache(const char* path) {
   while (fgets(line, sizeof(line), f)) {
     char key[512];
     Choice c;
-    if (sscanf(line, " \"%511[^\"]\": {\"variant\": %d, \"range_rows\": %lld, \"ms\": %lf}", key, &c.variant,
+    if (sscanf(line, " \"%511[^\"]\": {\"variant\": %d, \"range_rows\": %lld, \"range_group\": %d, \"ms\": %lf}",
+               key, &c.variant, &c.range_rows, &c.range_group, &c.ms) == 5 ||
+        sscanf(line, " \"%511[^\"]\": {\"variant\": %d, \"range_rows\": %lld, \"ms\": %lf}", key, &c.variant,
                &c.range_rows, &c.ms) == 4)
       m[key] = c;
   }
@@ -82,19 +86,22 @@ bool write_cache(const char* path, const std::map<std::string, Choice>& m) {
   fprintf(f, "{\n");
   size_t k = 0;
   for (const auto& kv : m) {
-    fprintf(f, " \"%s\": {\"variant\": %d, \"range_rows\": %lld, \"ms\": %.3f}%s\n", kv.first.c_str(),
-            kv.second.variant, kv.second.range_rows, kv.second.ms, ++k < m.size() ? "," : "");
+    fprintf(f, " \"%s\": {\"variant\": %d, \"range_rows\": %lld, \"range_group\": %d, \"ms\": %.3f}%s\n",
+            kv.first.c_str(), kv.second.variant, kv.second.range_rows, kv.second.range_group, kv.second.ms,
+            ++k < m.size() ? "," : "");
   }
   fprintf(f, "}\n");
   const bool ok = fclose(f) == 0;
   return ok && rename(tmp.c_str(), path) == 0;
 }
 
-// Kernel time of one self-join under (variant, range rows) on the index
-// that the join kernel runs on (the head-cut index for the screened join).
-int time_config(apss_index* ix, apss_index* target, float t, int variant, long long rr, double* ms) {
+// Kernel time of one self-join under (variant, range rows, ranges per item)
+// on the index that the join kernel runs on (the head-cut index for the
+// screened join).
+int time_config(apss_index* ix, apss_index* target, float t, int variant, long long rr, int rg, double* ms) {
   target->variant = variant;
   target->range_rows = rr;
+  target->range_group = rg;
   int64_t cnt = 0;
   int rc = ix->screen ? run_screen_join(ix, ix->ws, t, 16 * ix->n, &cnt)
                       : run_join(ix, ix->ws,
@@ -123,14 +130,17 @@ extern "C" int apss_autotune(apss_index* ix, float t, double budget_ms, const ch
     cache = read_cache(cache_path);
     auto it = cache.find(key);
     if (it != cache.end() && it->second.variant >= 0 && it->second.variant < join_num_variants() &&
-        variant_available(it->second.variant) && it->second.range_rows > 0) {
+        variant_available(it->second.variant) && it->second.range_rows > 0 && it->second.range_group >= 1 &&
+        it->second.range_group <= kMaxRangeGroup) {
       target->variant = it->second.variant;
       target->range_rows = it->second.range_rows;
+      target->range_group = it->second.range_group;
       // the chosen geometry's tables exist before the next join, which then
       // allocates none of them
       if ((rc = prepare(target, ix->ws.stream, target->variant, target->range_rows))) return rc;
       out->variant = it->second.variant;
       out->range_rows = (int32_t)it->second.range_rows;
+      out->range_group = it->second.range_group;
       out->ms = it->second.ms;
       out->from_cache = 1;
       return APSS_OK;
@@ -138,9 +148,16 @@ extern "C" int apss_autotune(apss_index* ix, float t, double budget_ms, const ch
   }
   const int v0 = target->variant;
   const long long r0 = target->range_rows;
+  const int g0 = target->range_group;
+  auto restore = [&]() {
+    target->variant = v0;
+    target->range_rows = r0;
+    target->range_group = g0;
+  };
   Choice best;
   best.variant = v0;
   best.range_rows = r0;
+  best.range_group = g0;
   best.ms = INFINITY;
   const auto start = std::chrono::steady_clock::now();
   // the current configuration first, so that a small budget still gives a valid choice
@@ -159,25 +176,48 @@ extern "C" int apss_autotune(apss_index* ix, float t, double budget_ms, const ch
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - start).count();
         if (tried > 0 && budget_ms > 0.0 && spent >= budget_ms) continue;
         double ms = 0.0;
-        if ((rc = time_config(ix, target, t, v, rr, &ms))) {
-          target->variant = v0;
-          target->range_rows = r0;
+        // the current configuration with its own ranges per item, the others with one
+        const int rg = current ? g0 : 1;
+        if ((rc = time_config(ix, target, t, v, rr, rg, &ms))) {
+          restore();
           return rc;
         }
         ++tried;
         if (ms < best.ms) {
           best.variant = v;
           best.range_rows = rr;
+          best.range_group = rg;
           best.ms = ms;
         }
       }
     }
   }
+  // then the ranges per item of the best geometry (an item stages its tile
+  // once for all of them)
+  const Choice geo = best;
+  for (int rg : {1, 2, 4, 8}) {
+    if (rg == geo.range_group) continue;
+    const double spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - start).count();
+    if (budget_ms > 0.0 && spent >= budget_ms) break;
+    double ms = 0.0;
+    if ((rc = time_config(ix, target, t, geo.variant, geo.range_rows, rg, &ms))) {
+      restore();
+      return rc;
+    }
+    ++tried;
+    if (ms < best.ms) {
+      best = geo;
+      best.range_group = rg;
+      best.ms = ms;
+    }
+  }
   target->variant = best.variant;
   target->range_rows = best.range_rows;
+  target->range_group = best.range_group;
   if ((rc = prepare(target, ix->ws.stream, target->variant, target->range_rows))) return rc;
   out->variant = best.variant;
   out->range_rows = (int32_t)best.range_rows;
+  out->range_group = best.range_group;
   out->ms = best.ms;
   out->tried = tried;
   if (cache_path && *cache_path) {

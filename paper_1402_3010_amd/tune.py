@@ -4,8 +4,9 @@
 
 For each workload the index is built as the benchmark builds it (the
 screened join for c4), and apss_autotune times every tile variant and range
-width of the join kernel at the workload's first threshold; the choice is
-merged into the JSON file, which the benchmark reads back.
+width of the join kernel at the workload's first threshold, then the number
+of ranges per work item; the choice is merged into the JSON file, which the
+benchmark reads back.
 """
 import argparse
 import os
@@ -43,9 +44,9 @@ def main():
             ix = apss.Index.build(dev, t, screen_dims=sd)
             t0 = time.perf_counter()
             r = ix.autotune(t, budget_ms=args.budget_ms, cache=args.out)
-            print("%s t=%.2f screen_dims=%d: variant %d, range %d rows, %.1f ms (%d tried, %.1f s)"
-                  % (name, t, sd, r["variant"], r["range_rows"], r["ms"], r["tried"], time.perf_counter() - t0),
-                  flush=True)
+            print("%s t=%.2f screen_dims=%d: variant %d, range %d rows, %d ranges per item, %.1f ms (%d tried, %.1f s)"
+                  % (name, t, sd, r["variant"], r["range_rows"], r["range_group"], r["ms"], r["tried"],
+                     time.perf_counter() - t0), flush=True)
             ix.close()
         del dev, V
 

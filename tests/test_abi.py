@@ -81,7 +81,7 @@ int main(void) {
   printf("apss_tune_result %zu\n", sizeof(apss_tune_result));
   F(apss_opts, stream) F(apss_opts, query_safe) F(apss_opts, variant) F(apss_opts, head_dims)
   F(apss_opts, range_rows) F(apss_opts, screen_dims) F(apss_opts, graph) F(apss_opts, index_all)
-  F(apss_opts, local_parts) F(apss_opts, remscore) F(apss_opts, reserved)
+  F(apss_opts, local_parts) F(apss_opts, remscore) F(apss_opts, range_group) F(apss_opts, reserved)
   F(apss_server_opts, slots) F(apss_server_opts, max_batch_queries) F(apss_server_opts, memory_budget)
   F(apss_server_opts, pairs_per_query) F(apss_server_opts, max_pending) F(apss_server_opts, split_queries)
   F(apss_server_opts, reserved)
@@ -92,6 +92,7 @@ int main(void) {
   F(apss_stats, ms_candidates) F(apss_stats, ms_total) F(apss_stats, screen_rows) F(apss_stats, screen_ld)
   F(apss_stats, ms_screen)
   F(apss_tune_result, ms) F(apss_tune_result, from_cache) F(apss_tune_result, cache_write_failed)
+  F(apss_tune_result, range_group)
   return 0;
 }
 """

@@ -296,6 +296,34 @@ def test_range_widths(apss, range_rows):
     assert st["matches"] == len(i)
 
 
+@pytest.mark.parametrize("variant,range_rows,range_group", [(1, 1024, 2), (1, 2048, 3), (2, 1024, 8), (0, 4096, 64),
+                                                          (1, 131072, 2)])
+def test_range_groups(apss, variant, range_rows, range_group):
+    # work items that stage their tile once and visit several ranges: the
+    # same pairs and candidates as one range per item, hashed and block
+    # ranges mixed within an item, groups cut short by the triangle and by
+    # the last range
+    V = make_corpus(spec_for("c2", n=9000))
+    t = np.float32(0.6)
+    i, j, s, st = gpu_join(apss, V, t, variant=variant, range_rows=range_rows, range_group=range_group)
+    assert_parity(i, j, s, oracle.join_plain(V, t), float(t), V)
+    pre = oracle.join_prefix(V, t, 4)
+    assert st["candidates"] == pre.candidates
+    i1, j1, s1, st1 = gpu_join(apss, V, t, variant=variant, range_rows=range_rows)
+    assert np.array_equal(i, i1) and np.array_equal(j, j1) and np.array_equal(s.view(np.uint32), s1.view(np.uint32))
+    assert st["posting_visits"] == st1["posting_visits"]
+    # queries against the index (no triangle), per-row thresholds
+    Q = V.take_rows(np.arange(5, 9000, 61))
+    tq = np.random.default_rng(11).uniform(0.5, 0.9, size=Q.n).astype(np.float32)
+    ix = apss.Index.build(V, np.float32(0.5), variant=variant, range_rows=range_rows, range_group=range_group)
+    try:
+        qi, qy, qs = ix.query(Q, t_per_row=tq)
+    finally:
+        ix.close()
+    assert_parity(qi, qy, qs, oracle.query(V, Q, t_per_row=tq.astype(np.float64)), None, Q, V,
+                  per_row_t=tq.astype(np.float64))
+
+
 def test_query_device_input_matches_host(apss):
     # the same queries given as device tensors take the device staging path
     # (row offsets checked on the device); the pairs are bitwise the same

@@ -70,6 +70,17 @@ def test_screened_equals_plain_and_oracle(apss, name, n, t, sd):
     assert_parity(scr[0], scr[1], scr[2], oracle.join_plain(V, np.float32(t)), float(np.float32(t)), V)
 
 
+def test_screened_range_groups(apss):
+    # the sparse pass with several ranges per work item (its tuned form at
+    # full size): the plain join's pairs bit for bit
+    V = make_corpus(spec_for("c4", n=20000))
+    t = 0.8
+    plain = join(apss, V, t)
+    for kw in (dict(variant=2, range_rows=2048, range_group=4), dict(variant=1, range_rows=1024, range_group=3)):
+        scr = join(apss, V, t, screen_dims=4096, **kw)
+        assert_identical(plain, scr)
+
+
 def test_screen_finds_pairs_with_no_tail_overlap(apss):
     """Near-duplicate rows that live almost entirely in the head: the
     matches must come from the MFMA screen (the sparse pass cannot see them)."""
