@@ -190,6 +190,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
   constexpr int NW = NT / 64;
   constexpr int KMAX = QB / NT;  // staged components per thread
   constexpr int YPT = CB / NT;   // corpus rows per thread in the filter
+  // with the register budget of two waves per SIMD, the list offsets of an
+  // item's next range are loaded while the current range is processed
+  constexpr bool PF = C::WPE <= 2;
   static_assert(KMAX >= 1 && QB % NT == 0 && CB % NT == 0, "tile geometry");
   static_assert(CB <= 65536 && QT <= 256, "survivor packing");
   static_assert(SQ >= 128, "survivor queue");
@@ -363,6 +366,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
     }
   }
 
+  uint32_t pc[KMAX], pn[KMAX];  // (PF) the next range's first and end offsets of this thread's components
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) pc[j] = pn[j] = 0u;
   for (int64_t R = R0; R <= R1; ++R) {
   if (R > R0) {
     // the previous range is done with the per-range fields
@@ -409,12 +415,20 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       if (k < tile_nnz) {
         // dense lists by block offsets, sparse ones by range offsets
         const bool dense = r < a.H;
-        const uint32_t* t0 = dense ? a.hoff + b_begin * (int64_t)a.H + r : a.toff + R * (int64_t)a.m_tail + (r - a.H);
-        const uint32_t* t1 = dense ? a.hoff + b_end * (int64_t)a.H + r : a.toff + (R + 1) * (int64_t)a.m_tail + (r - a.H);
-        p0[j] = *t0;
-        p1[j] = *t1;
-        // the next block's segment end of a dense list (b_begin + 1 <= nb)
-        hn[j] = dense ? a.hoff[(b_begin + 1) * (int64_t)a.H + r] : 0u;
+        if (PF && R > R0) {
+          p0[j] = pc[j];
+          p1[j] = pn[j];
+        } else {
+          const uint32_t* t0 =
+              dense ? a.hoff + b_begin * (int64_t)a.H + r : a.toff + R * (int64_t)a.m_tail + (r - a.H);
+          const uint32_t* t1 =
+              dense ? a.hoff + b_end * (int64_t)a.H + r : a.toff + (R + 1) * (int64_t)a.m_tail + (r - a.H);
+          p0[j] = *t0;
+          p1[j] = *t1;
+        }
+        // the next block's segment end of a dense list (b_begin + 1 <= nb);
+        // with PF loaded by the block path when a range takes it
+        if (!PF) hn[j] = dense ? a.hoff[(b_begin + 1) * (int64_t)a.H + r] : 0u;
       }
     }
 #pragma unroll
@@ -432,7 +446,7 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         // once the range is known to take that path
         sm.cur[k] = make_uint2(dead ? kDead : p0[j], 0u);
       }
-      if (dead) hn[j] = 0u;
+      if (!PF && dead) hn[j] = 0u;
       // the component's entries in the whole range, for a hashed item
       // (whose segments are all short enough for the 16-bit length)
       const uint64_t m = __ballot(!dead);
@@ -446,6 +460,21 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
         // bit 31 (remscore): the component admits; the 24-bit product ignores it
         sg.q = q15(c.w) | (REM && admits ? 0x80000000u : 0u);
         sm.seg[QB - 1 - (base + (int)__popcll(m & lt))] = sg;
+      }
+    }
+    if constexpr (PF) {
+      // the next range starts where this one ends; its ends are loaded now
+      // and waited for only when that range is staged
+      if (R < R1) {
+        const int64_t nend = ((R + 2) * a.K) < (last_b + 1) ? ((R + 2) * a.K) : (last_b + 1);
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+          const int k = j * NT + tid;
+          const int32_t r = cc[j].r;
+          pc[j] = p1[j];
+          if (k < tile_nnz)
+            pn[j] = r < a.H ? a.hoff[nend * (int64_t)a.H + r] : a.toff[(R + 2) * (int64_t)a.m_tail + (r - a.H)];
+        }
       }
     }
   } else if (b_begin < b_end) {
@@ -892,6 +921,15 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
       for (int64_t k = tid; k < tile_nnz; k += NT) {
         const uint2 cu = sm.cur[k];
         if (cu.x != kDead && sm.qrow[k].r >= a.H) sm.cur[k] = make_uint2(cu.x, a.post[cu.x].y);
+      }
+      if constexpr (PF) {
+        // the next block's segment ends of the live dense lists
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+          const int k = j * NT + tid;
+          const int32_t r = sm.qrow[k].r;
+          hn[j] = (k < tile_nnz && sm.cur[k].x != kDead && r < a.H) ? a.hoff[(b_begin + 1) * (int64_t)a.H + r] : 0u;
+        }
       }
     }
     __syncthreads();
