@@ -33,6 +33,10 @@ struct RowStat {
   float pnrm;
 };
 
+// One-byte upper bound of a row's unindexed-part norm: code k < 255 means
+// pnrm <= k / 254; kPn8None means no bound.
+constexpr uint8_t kPn8None = 255;
+
 // Counters written by the join kernels (uint64 slots).
 enum Counter {
   C_VISITS = 0,

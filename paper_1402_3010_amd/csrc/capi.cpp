@@ -267,11 +267,13 @@ int build_lists(apss_index* ix) {
                     ix->rs.p, ix->rows.mw.p, nidx.p, s),
       "cutoff");
   CHK(exclusive_scan_i64(nidx.p, n, scan_tmp.p, total.p, s), "scan");
-  // the largest unindexed-part norm: the hashed filter's test without row statistics
+  // the largest unindexed-part norm and each row's as a byte: the hashed
+  // filter's tests before it reads a row's statistics
   DBuf<uint32_t> pmax;
   CHK(pmax.alloc(1), "alloc");
+  CHK(ix->pn8.alloc(std::max<int64_t>(n, 1)), "alloc");
   CHK(fill_u32(pmax.p, 0u, 1, s), "fill");
-  CHK(launch_max_pnrm(ix->rs.p, n, pmax.p, s), "max norm");
+  CHK(launch_max_pnrm(ix->rs.p, n, pmax.p, ix->pn8.p, s), "max norm");
   int64_t P = 0;
   uint32_t pmax_bits = 0u;
   CHK(hipMemcpyAsync(&P, total.p, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read P");
@@ -509,6 +511,7 @@ void bind_plan(apss_index* ix, const QuerySet& Q, int triangle, float t, const f
   a.rc = ix->rows.rc.p;
   a.rs = ix->rs.p;
   a.pnrm_max = ix->pnrm_max;
+  a.pn8 = ix->pn8.p;
   a.off = ix->off.p;
   a.post = ix->post.p;
   a.post4 = ix->post4.p;

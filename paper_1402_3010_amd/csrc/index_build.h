@@ -36,7 +36,7 @@ hipError_t launch_emit_indexed(const int64_t* rp, const RComp* rc, const RowStat
 hipError_t launch_count_ranks(const uint64_t* keys, int64_t P, int64_t* cnt, hipStream_t s);
 hipError_t launch_unpack_post(const uint64_t* vals, int64_t P, Post* post, hipStream_t s);
 // *out = max over rows of rs[r].pnrm as float bits (atomicMax; *out zeroed before)
-hipError_t launch_max_pnrm(const RowStat* rs, int64_t n, uint32_t* out, hipStream_t s);
+hipError_t launch_max_pnrm(const RowStat* rs, int64_t n, uint32_t* out, uint8_t* pn8, hipStream_t s);
 hipError_t launch_pack_post4(const Post* post, int64_t P, uint32_t* post4, hipStream_t s);
 hipError_t launch_block_offsets(const int64_t* off, const Post* post, int32_t H, int64_t nb, int32_t CB,
                                 uint32_t* hoff, hipStream_t s);

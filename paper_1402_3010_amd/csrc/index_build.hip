@@ -160,11 +160,17 @@ __global__ void k_cutoff(const int64_t* __restrict__ rp, const RComp* __restrict
 }
 
 // Largest unindexed-part norm over the rows (norms are >= 0, so their bit
-// patterns order like the values).
-__global__ void k_max_pnrm(const RowStat* __restrict__ rs, int64_t n, uint32_t* __restrict__ out) {
+// patterns order like the values), and each row's norm as a one-byte upper
+// bound: the smallest k with pnrm <= k / 254 (in double), or kPn8None.
+__global__ void k_max_pnrm(const RowStat* __restrict__ rs, int64_t n, uint32_t* __restrict__ out,
+                           uint8_t* __restrict__ pn8) {
   uint32_t m = 0u;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    m = max(m, __float_as_uint(rs[r].pnrm));
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const float p = rs[r].pnrm;
+    m = max(m, __float_as_uint(p));
+    const double k = ceil((double)p * 254.0);
+    pn8[r] = k <= 254.0 ? (uint8_t)k : kPn8None;
+  }
   if (m) atomicMax(out, m);
 }
 
@@ -355,9 +361,9 @@ hipError_t launch_unpack_post(const uint64_t* vals, int64_t P, Post* post, hipSt
   return hipSuccess;
 }
 
-hipError_t launch_max_pnrm(const RowStat* rs, int64_t n, uint32_t* out, hipStream_t s) {
+hipError_t launch_max_pnrm(const RowStat* rs, int64_t n, uint32_t* out, uint8_t* pn8, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  LAUNCH(k_max_pnrm, n, rs, n, out);
+  LAUNCH(k_max_pnrm, n, rs, n, out, pn8);
   return hipSuccess;
 }
 

@@ -15,6 +15,7 @@ struct JoinArgs {
   const RComp* rc;        // [nnz] components, densest dimension first
   const RowStat* rs;      // [n]
   float pnrm_max;         // max over rows of rs[y].pnrm
+  const uint8_t* pn8;     // [n] rs[y].pnrm as a byte code (kPn8None: no bound; else pnrm <= code / 254)
   const int64_t* off;     // [m+1] list offsets by rank
   const Post* post;       // [P+2] list entries, vector ids ascending within a list; 2 padding entries
   const uint32_t* post4;  // [P+kPost4Pad] the same entries packed: id mod 2^16 | weight in 2^-15 units (rounded up) << 16
@@ -68,7 +69,7 @@ struct JoinArgs {
 
 // True when every device buffer the join kernel dereferences is present.
 inline bool join_args_complete(const JoinArgs& a) {
-  return a.rp && a.rc && a.rs && a.off && a.post && a.post4 && a.hoff && a.qrp && a.qrc && a.qmw && a.toff && a.tstart &&
+  return a.rp && a.rc && a.rs && a.pn8 && a.off && a.post && a.post4 && a.hoff && a.qrp && a.qrc && a.qmw && a.toff && a.tstart &&
          a.qcum && a.qctr && a.wg_cur && a.out_key && a.out_sim && a.counters;
 }
 

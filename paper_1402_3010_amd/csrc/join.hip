@@ -66,6 +66,11 @@ __device__ __forceinline__ uint32_t q15(float w) {
 }
 __device__ __forceinline__ uint32_t packed_product(uint32_t q, uint32_t e) { return __umul24(q, e >> 16); }
 
+// Upper bound of a row's unindexed-part norm from its byte code.  Rounding
+// of the product and sum it enters stays far inside the 4,096 accumulator
+// units (4e-6 of a score) by which the filters' byte tests are loosened.
+__device__ __forceinline__ float pn8_bound(uint8_t k) { return k == kPn8None ? 3.0e38f : (float)k * (1.0f / 254.0f); }
+
 // (p & mask) | base in one instruction (the compiler turns the OR of
 // disjoint bits back into an add and spends three instructions on it)
 __device__ __forceinline__ uint32_t and_or(uint32_t p, uint32_t mask, uint32_t base) {
@@ -791,6 +796,8 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
           uint32_t kk[G], hv[G];
           int64_t yv[G];
           bool ok[G], pre[G];
+          float qw[G], qx[G];
+          uint8_t k8[G];
           RowStat stg[G];
 #pragma unroll
           for (int g = 0; g < G; ++g) {
@@ -801,11 +808,26 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             yv[g] = rbeg + (int64_t)((kk[g] - 1u) & 0xFFFFu);
             ok[g] = kk[g] != 0u && yv[g] < a.n && !(a.triangle && yv[g] >= q0 + qi);
             if constexpr (REM) ok[g] = ok[g] && ((sm.adm[h >> 5] >> (h & 31)) & 1u);
-            // the L2 bound with the largest unindexed-part norm of any row:
-            // a candidate that fails it cannot survive and needs no row statistics
+            // the L2 bound with the largest unindexed-part norm of any row,
+            // then with the row's own norm as a byte: a candidate that fails
+            // either cannot survive and needs no row statistics
             const float4 qbq = sm.qb[ok[g] ? qi : 0];
-            pre[g] = ok[g] && (float)hv[g] + qbq.w * a.pnrm_max >= qbq.x - 4096.0f;
-            stg[g] = a.rs[pre[g] ? yv[g] : 0];
+            qw[g] = qbq.w;
+            qx[g] = qbq.x - 4096.0f;
+            pre[g] = ok[g] && (float)hv[g] + qbq.w * a.pnrm_max >= qx[g];
+            k8[g] = a.pn8[pre[g] ? yv[g] : 0];
+          }
+          bool need = false;
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            pre[g] = pre[g] && (float)hv[g] + qw[g] * pn8_bound(k8[g]) >= qx[g];
+            need = need || pre[g];
+            stg[g] = RowStat{0, 0, 0.0f, 0.0f};
+          }
+          // row statistics only where a lane of the wave still needs them
+          if (__ballot(need)) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) stg[g] = a.rs[pre[g] ? yv[g] : 0];
           }
 #pragma unroll
           for (int g = 0; g < G; ++g) {
@@ -867,8 +889,9 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::WPE)))
             if (adm_ok && y < a.n && !(a.triangle && y >= q0 + qi)) {
               const float4 qb = sm.qb[qi];
               const float A = (float)av;  // accumulator units, as the bounds
-              // the L2 bound with the largest unindexed-part norm of any row first
-              if (A + qb.w * a.pnrm_max >= qb.x - 4096.0f) {
+              // the L2 bound with the largest unindexed-part norm of any row
+              // first, then with the row's own norm as a byte
+              if (A + qb.w * a.pnrm_max >= qb.x - 4096.0f && A + qb.w * pn8_bound(a.pn8[y]) >= qb.x - 4096.0f) {
                 const RowStat st = a.rs[y];
                 const int ylen = st.len;
                 packed = (uint32_t)(st.cut < 0xFFFF ? st.cut : 0xFFFF) | ((uint32_t)(ylen < 0xFFFF ? ylen : 0xFFFF) << 16);

@@ -177,6 +177,7 @@ struct apss_index {
   apss::DBuf<int64_t> off;
   apss::DBuf<apss::Post> post;
   apss::DBuf<uint32_t> post4;  // packed copy of post for streaming
+  apss::DBuf<uint8_t> pn8;     // [n] RowStat.pnrm as a byte code (kPn8None or an upper bound in 1/254 steps)
   // local pruning: rank bounds of the parts (parts + 1 entries)
   int32_t parts = 1;
   apss::DBuf<int32_t> part_lo;
