@@ -323,6 +323,9 @@ def variants_bench(args):
             for label, kw in VARIANTS:
                 ix = apss.Index.build(dev, t, variant=1, range_rows=16384, **kw)
                 try:
+                    # the first join sizes the pair buffers (a join whose pairs
+                    # overflow them runs its kernel again); the second is timed
+                    ix.join(t)
                     i, _, _ = ix.join(t)
                     cnt = len(i)
                     st = ix.stats()
