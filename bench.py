@@ -392,8 +392,12 @@ def serve_bench(args):
     log("serve saturation: %d requests, %d queries in %.2f s: %.1f req/s, %.0f queries/s"
         % (len(burst), nq_burst, el, sat_rps, sat_qps))
     curve = []
-    for frac in args.serve_load:
-        rate = frac * sat_rps
+    # open-loop runs at fractions of the saturation rate, then at fixed
+    # offered query rates (request rate = query rate / mean request size)
+    mean_nq = nq_burst / len(burst)
+    points = [(frac, frac * sat_rps) for frac in args.serve_load]
+    points += [(None, qps / mean_nq) for qps in args.serve_qps]
+    for frac, rate in points:
         n_req = max(40, int(rate * args.serve_seconds))
         reqs = requests(pool, n_req)
         arr = np.cumsum(rng.exponential(1.0 / rate, size=n_req)).tolist()
@@ -404,7 +408,8 @@ def serve_bench(args):
         nq = sum(Q.n for Q, _ in reqs)
         small = [r[1] for r in res if reqs[r[0]][0].n <= 256]
         large = [r[1] for r in res if reqs[r[0]][0].n > 256]
-        point = {"load": frac, "rate_rps": rate, "requests": n_req, "queries": nq,
+        point = {"load": frac if frac is not None else rate * mean_nq / sat_qps, "rate_rps": rate,
+                 "offered_qps": rate * mean_nq, "requests": n_req, "queries": nq,
                  "qps": nq / el, "rps": n_req / el, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
                  "p99_ms_requests_le_256_queries": percentile(small, 99),
                  "p99_ms_requests_gt_256_queries": percentile(large, 99),
@@ -415,7 +420,8 @@ def serve_bench(args):
         curve.append(point)
         log("serve load %.2f: %.1f req/s offered, %.0f queries/s, p50 %.1f ms, p99 %.1f ms "
             "(requests of <= 256 queries: p99 %.1f ms)"
-            % (frac, rate, point["qps"], point["p50_ms"], point["p99_ms"], point["p99_ms_requests_le_256_queries"] or 0.0))
+            % (point["load"], rate, point["qps"], point["p50_ms"], point["p99_ms"],
+               point["p99_ms_requests_le_256_queries"] or 0.0))
     # the middle load once more on queries without corpus copies
     frac = args.serve_load[len(args.serve_load) // 2]
     rate = frac * sat_rps
@@ -429,7 +435,7 @@ def serve_bench(args):
     st = srv.stats()
     srv.close()
     ix.close()
-    mid = curve[len(curve) // 2]
+    mid = curve[len(args.serve_load) // 2]
     return {
         "workload": "c5: resident index of %d vectors, m=%d, nnz/vector lognormal mean 100 (5..2000), Zipf s=1.0, "
                     "t_build=0.5; requests of 1..4096 queries (log-uniform), query nnz lognormal mean 100, "
@@ -440,6 +446,7 @@ def serve_bench(args):
         "qps": mid["qps"], "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"], "at_load": mid["load"],
         "saturation_qps": sat_qps, "saturation_rps": sat_rps,
         "curve": curve,
+        "at_fixed_qps": [p for p in curve[len(args.serve_load):]],
         "no_copies": fresh,
         "peak_running_batches": st["peak_running"], "overlapped_batches": st["overlapped_batches"],
         "regrows": st["regrows"], "failed": st["failed"],
@@ -473,6 +480,8 @@ def main():
                     help="queue requests of more rows as pieces of at most this many rows (0: whole requests)")
     ap.add_argument("--serve-requests", type=int, default=120, help="requests in the saturation burst")
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="length of each open-loop run")
+    ap.add_argument("--serve-qps", type=float, nargs="*", default=[180000.0],
+                    help="also run at these offered query rates")
     ap.add_argument("--serve-load", type=float, nargs="+", default=[0.3, 0.6, 0.9],
                     help="offered load as fractions of the saturation request rate")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",

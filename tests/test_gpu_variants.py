@@ -171,7 +171,10 @@ def test_remscore_combinations_and_queries(apss):
                # every tile variant, and narrow ranges whose items take the hashed path
                dict(remscore=True, variant=0), dict(remscore=True, variant=2), dict(remscore=True, range_rows=1024),
                dict(remscore=True, variant=2, range_rows=2048, local_parts=2),
-               dict(local_parts=8, variant=0), dict(local_parts=2, range_rows=1024), dict(index_all=True, variant=2)):
+               dict(local_parts=8, variant=0), dict(local_parts=2, range_rows=1024), dict(index_all=True, variant=2),
+               # work items over several ranges
+               dict(remscore=True, range_rows=1024, range_group=3), dict(local_parts=2, range_rows=2048, range_group=2),
+               dict(index_all=True, variant=2, range_rows=1024, range_group=4)):
         res = join(apss, V, t, **kw)
         assert_parity(res[0], res[1], res[2], ref, float(t), V)
         assert_identical(base, res)

@@ -33,10 +33,10 @@ def host(bufs, n):
     return (i[:n].cpu().numpy().astype(np.uint32), j[:n].cpu().numpy().astype(np.uint32), s[:n].cpu().numpy())
 
 
-def one_case(apss, V, t):
+def one_case(apss, V, t, **kw):
     t = np.float32(t)
-    print("noalloc case n=%d t=%.2f" % (V.n, t), flush=True)
-    ix = apss.Index.build(V, t, on_device=True)
+    print("noalloc case n=%d t=%.2f %s" % (V.n, t, kw), flush=True)
+    ix = apss.Index.build(V, t, on_device=True, **kw)
     try:
         ref_i, _, _ = ix.join(t)
         n = len(ref_i)
@@ -66,6 +66,15 @@ def test_noalloc_matches_join_device_two_calls(apss):
     small = make_corpus(spec_for("c2", n=5000, seed=77))
     n1 = one_case(apss, big, 0.6)
     n2 = one_case(apss, small, 0.6)
+    assert n1 > n2 > 0
+
+
+def test_noalloc_with_range_groups(apss):
+    # work items over several ranges use the same scratch layout
+    big = make_corpus(spec_for("c2", n=21111))
+    small = make_corpus(spec_for("c2", n=5000, seed=77))
+    n1 = one_case(apss, big, 0.6, range_rows=2048, range_group=3)
+    n2 = one_case(apss, small, 0.6, variant=2, range_rows=1024, range_group=4)
     assert n1 > n2 > 0
 
 
