@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <new>
 #include <string>
 #include <vector>
@@ -744,6 +745,26 @@ int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, in
       }
     }
     ntiles = (int64_t)tl.size() / 2;
+    // blocks of kScreenBlock x kScreenBlock tiles in turn: the workgroups
+    // that run at once on an XCD then share a few panels of each operand
+    // (from L2 and the last-level cache) instead of streaming a new second
+    // operand panel per tile from HBM (C4: 8.0 -> 6.6 ms; blocks of 4 and
+    // 16 tiles measured within 0.1 ms of 8, of 32 tiles 7.5 ms)
+    {
+      const int B = kScreenBlock;
+      if (B > 1) {
+        std::vector<std::array<int32_t, 4>> key((size_t)ntiles);
+        for (int64_t k = 0; k < ntiles; ++k) {
+          const int32_t I = tl[(size_t)(2 * k)], J = tl[(size_t)(2 * k + 1)];
+          key[(size_t)k] = {I / B, J / B, I, J};
+        }
+        std::sort(key.begin(), key.end());
+        for (int64_t k = 0; k < ntiles; ++k) {
+          tl[(size_t)(2 * k)] = key[(size_t)k][2];
+          tl[(size_t)(2 * k + 1)] = key[(size_t)k][3];
+        }
+      }
+    }
     if (ntiles > 0) {
       CHK(ws.s_tiles.reserve((int64_t)tl.size()), "alloc screen");
       CHK(hipMemcpyAsync(ws.s_tiles.p, tl.data(), sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice, s),

@@ -8,6 +8,8 @@ namespace apss {
 // Output tile edge of the screen kernel and the K step its operands are
 // padded to (the packed head block has ld = head rounded up to kScreenK).
 constexpr int kScreenTile = 128;
+// tiles per side of the blocks in which the screen visits its tile list
+constexpr int kScreenBlock = 8;
 constexpr int kScreenK = 64;
 
 // Screen margin coefficient: for bf16 (round to nearest even) copies of the
