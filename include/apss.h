@@ -186,7 +186,8 @@ typedef struct {
   double ms_total;          /* device time of the whole call (kernels + sort) */
   /* screened join only (zero otherwise) */
   int64_t screen_rows;        /* rows whose head norm reaches t */
-  int64_t screen_tiles;       /* 128 x 128 tiles of the head screen (each 2 * 128 * 128 * ld flops) */
+  int64_t screen_tiles;       /* 128 x 128 row-tile pairs of the head screen whose norm bound reaches t
+                                 (2 * 128 * 128 * ld flops of useful work each) */
   int64_t screen_candidates;  /* pairs passing the screen's widened threshold */
   int64_t screen_ld;          /* head dimensions padded to the screen's K step */
   double ms_screen;           /* device time of the screen's MFMA kernel */

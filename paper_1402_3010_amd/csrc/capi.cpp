@@ -714,8 +714,8 @@ int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, in
   CHK(hipMemcpyAsync(&S64, ws.s_cnt.p, sizeof(S64), hipMemcpyDeviceToHost, s), "screen select");
   CHK(hipStreamSynchronize(s), "screen select");
   const int64_t S = (int64_t)S64;
-  const int64_t Sp = (S + kScreenTile - 1) / kScreenTile * kScreenTile;
-  int64_t nc = 0, ntiles = 0;
+  const int64_t Sp = (S + kScreenTileB - 1) / kScreenTileB * kScreenTileB;
+  int64_t nc = 0, ntiles = 0, useful = 0;
   if (S > 1) {
     SortScratch& ss = ws.ss;
     CHK(ss.k2.reserve(S), "alloc sort");
@@ -730,33 +730,40 @@ int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, in
     CHK(ws.s_X.reserve(Sp * ld), "alloc screen block");
     CHK(fill_u32((uint32_t*)ws.s_X.p, 0u, Sp * ld / 2, s), "fill");
     CHK(launch_screen_pack(sx->rows.rp.p, sx->rows.rc.p, ws.s_sid.p, S, head, ld, ws.s_X.p, s), "screen pack");
-    // tiles (I, J), I <= J, whose largest norm product reaches t
-    std::vector<float> nh((size_t)S);
-    CHK(hipMemcpyAsync(nh.data(), ws.s_nh.p, sizeof(float) * S, hipMemcpyDeviceToHost, s), "screen norms");
+    // tiles (I, J) of kScreenTile x kScreenTileB rows that reach the upper
+    // triangle (2 J + 1 >= I) and whose largest norm product reaches t (rows
+    // are in decreasing head norm, so a tile's first rows have the largest);
+    // `useful` counts the kScreenTile x kScreenTile pairs I <= J among them
+    std::vector<float> nh((size_t)Sp);
+    CHK(hipMemcpyAsync(nh.data(), ws.s_nh.p, sizeof(float) * Sp, hipMemcpyDeviceToHost, s), "screen norms");
     CHK(hipStreamSynchronize(s), "screen norms");
-    const int64_t T = Sp / kScreenTile;
+    const int64_t T = Sp / kScreenTile, TB = Sp / kScreenTileB;
     std::vector<int32_t> tl;
     for (int64_t I = 0; I < T; ++I) {
       const float nI = nh[(size_t)(I * kScreenTile)];
       for (int64_t J = I; J < T; ++J) {
         if (nI * nh[(size_t)(J * kScreenTile)] * (1.0f + 0x1p-20f) < t) break;
+        ++useful;
+      }
+      for (int64_t J = I / 2; J < TB; ++J) {
+        if (nI * nh[(size_t)(J * kScreenTileB)] * (1.0f + 0x1p-20f) < t) break;
         tl.push_back((int32_t)I);
         tl.push_back((int32_t)J);
       }
     }
     ntiles = (int64_t)tl.size() / 2;
-    // blocks of kScreenBlock x kScreenBlock tiles in turn: the workgroups
-    // that run at once on an XCD then share a few panels of each operand
-    // (from L2 and the last-level cache) instead of streaming a new second
-    // operand panel per tile from HBM (C4: 8.0 -> 6.6 ms; blocks of 4 and
-    // 16 tiles measured within 0.1 ms of 8, of 32 tiles 7.5 ms)
+    // blocks of kScreenBlock x kScreenBlock row tiles in turn: the
+    // workgroups that run at once on an XCD then share a few panels of each
+    // operand (from L2 and the last-level cache) instead of streaming a new
+    // second operand panel per tile from HBM (C4 with 128 x 128 tiles:
+    // 8.0 -> 6.6 ms; blocks of 4 and 16 within 0.1 ms of 8, of 32 7.5 ms)
     {
       const int B = kScreenBlock;
       if (B > 1) {
         std::vector<std::array<int32_t, 4>> key((size_t)ntiles);
         for (int64_t k = 0; k < ntiles; ++k) {
           const int32_t I = tl[(size_t)(2 * k)], J = tl[(size_t)(2 * k + 1)];
-          key[(size_t)k] = {I / B, J / B, I, J};
+          key[(size_t)k] = {I / B, J / (B * kScreenTile / kScreenTileB), I, J};
         }
         std::sort(key.begin(), key.end());
         for (int64_t k = 0; k < ntiles; ++k) {
@@ -835,7 +842,7 @@ int run_screen_join(apss_index* ix, Workspace& ws, float t, int64_t cap_hint, in
     take_counters(ws, c);
     ws.last.ms_screen = ms_screen;
     ws.last.screen_rows = S;
-    ws.last.screen_tiles = ntiles;
+    ws.last.screen_tiles = useful;
     ws.last.screen_candidates = nc;
     ws.last.screen_ld = ld;
     float ms = 0.0f;

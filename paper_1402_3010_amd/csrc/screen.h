@@ -5,10 +5,14 @@
 
 namespace apss {
 
-// Output tile edge of the screen kernel and the K step its operands are
-// padded to (the packed head block has ld = head rounded up to kScreenK).
+// Output tile of the screen kernel: kScreenTile rows of the packed block
+// (the unit of its panels) against kScreenTileB = two such row tiles; the
+// packed rows are padded to kScreenTileB.  kScreenK is the K step the
+// operands are padded to (the packed head block has ld = head rounded up to
+// kScreenK).
 constexpr int kScreenTile = 128;
-// tiles per side of the blocks in which the screen visits its tile list
+constexpr int kScreenTileB = 2 * kScreenTile;
+// row tiles per side of the blocks in which the screen visits its tile list
 constexpr int kScreenBlock = 8;
 constexpr int kScreenK = 64;
 
@@ -35,7 +39,8 @@ struct ScreenArgs {
   int32_t ld;          // multiple of kScreenK
   const float* nh;     // [Sp] head norms (rounded up), 0 for padding
   const int32_t* sid;  // [Sp] row ids
-  const int32_t* tiles;  // [2 * ntiles] (I, J), I <= J, tile indices in units of kScreenTile rows
+  const int32_t* tiles;  // [2 * ntiles] (I, J): rows I * kScreenTile.. against rows J * kScreenTileB..,
+                         // with 2 J + 1 >= I (the tile reaches the upper triangle)
   int64_t ntiles;
   float t;
   int32_t bj;

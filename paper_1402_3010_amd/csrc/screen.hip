@@ -99,11 +99,13 @@ __global__ void k_screen_pack(const int64_t* __restrict__ rp, const RComp* __res
   }
 }
 
-// One workgroup (4 waves) per 128 x 128 output tile (I, J) of the packed
-// rows; wave w owns the 64 x 64 quarter (w / 2, w % 2) as 2 x 2 MFMA blocks
-// of 32 x 32 (v_mfma_f32_32x32x16_bf16, float accumulation).  Lane l of a
-// 32 x 32 x 16 MFMA holds operand row (l % 32), k = 8 (l / 32) .. + 7; result
-// element r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+// One workgroup (4 waves) per output tile of 128 x 256 packed rows (row
+// tile I against the two row tiles 2J, 2J + 1); wave w owns the 64 x 128
+// part (w / 2, w % 2) as 2 x 4 MFMA blocks of 32 x 32
+// (v_mfma_f32_32x32x16_bf16, float accumulation), so that every operand
+// fragment read from LDS feeds two or four MFMAs.  Lane l of a 32 x 32 x 16
+// MFMA holds operand row (l % 32), k = 8 (l / 32) .. + 7; result element r of
+// lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
 //
 // K advances in steps of 32 through two LDS buffers.  Each buffer row is 32
 // bf16 = four 16-byte chunks; chunk c of row r is stored at position
@@ -115,50 +117,57 @@ constexpr int kStepK = 32;
 __device__ __forceinline__ int swz(int row, int c) { return row * 4 + (c ^ ((row >> 2) & 3)); }
 
 template <bool DUMP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_screen_mfma(ScreenArgs a, int64_t chunk) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_screen_mfma(ScreenArgs a, int64_t chunk) {
   __shared__ u32x4 As[2][kScreenTile * 4];
-  __shared__ u32x4 Bs[2][kScreenTile * 4];
+  __shared__ u32x4 Bs[2][kScreenTileB * 4];
   // the workgroups of one XCD (round-robin over blockIdx) take one
-  // contiguous chunk of the tile list, which is ordered by I
+  // contiguous chunk of the tile list, which is ordered in blocks
   const int64_t ti = (int64_t)(blockIdx.x & 7u) * chunk + (int64_t)(blockIdx.x >> 3);
   if (ti >= a.ntiles) return;
   const int I = a.tiles[2 * ti], J = a.tiles[2 * ti + 1];
-  const int64_t a0 = (int64_t)I * kScreenTile, b0 = (int64_t)J * kScreenTile;
+  const int64_t a0 = (int64_t)I * kScreenTile, b0 = (int64_t)J * kScreenTileB;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
   const int nks = a.ld / kStepK;
 
-  // this thread's two chunks of each operand per step: rows tid / 4 and
-  // tid / 4 + 64, chunk tid % 4, in the contiguous 8 KB panel of the step
+  // this thread's chunks of each operand per step: rows tid / 4 + 64 h of
+  // the step's contiguous 8 KB panels (one panel of the first operand's row
+  // tile, two of the second's), chunk tid % 4
   const int lrow = tid >> 2, lc = tid & 3;
   const uint16_t* pa0 = a.X + (((int64_t)I * nks) << 12) + lrow * 32 + lc * 8;
   const uint16_t* pa1 = pa0 + 64 * 32;
-  const uint16_t* pb0 = a.X + (((int64_t)J * nks) << 12) + lrow * 32 + lc * 8;
+  const uint16_t* pb0 = a.X + (((int64_t)(2 * J) * nks) << 12) + lrow * 32 + lc * 8;
   const uint16_t* pb1 = pb0 + 64 * 32;
-  const int s0 = swz(lrow, lc), s1 = swz(lrow + 64, lc);
+  const uint16_t* pb2 = a.X + (((int64_t)(2 * J + 1) * nks) << 12) + lrow * 32 + lc * 8;
+  const uint16_t* pb3 = pb2 + 64 * 32;
+  const int s0 = swz(lrow, lc), s1 = swz(lrow + 64, lc), s2 = swz(lrow + 128, lc), s3 = swz(lrow + 192, lc);
 
-  u32x4 r0[4], r1[4];
-  auto ldg = [&](int ks, u32x4 (&r)[4]) {
+  u32x4 r0[6], r1[6];
+  auto ldg = [&](int ks, u32x4 (&r)[6]) {
     const int64_t o = (int64_t)ks << 12;
     r[0] = *reinterpret_cast<const u32x4*>(pa0 + o);
     r[1] = *reinterpret_cast<const u32x4*>(pa1 + o);
     r[2] = *reinterpret_cast<const u32x4*>(pb0 + o);
     r[3] = *reinterpret_cast<const u32x4*>(pb1 + o);
+    r[4] = *reinterpret_cast<const u32x4*>(pb2 + o);
+    r[5] = *reinterpret_cast<const u32x4*>(pb3 + o);
   };
-  auto sts = [&](int buf, const u32x4 (&r)[4]) {
+  auto sts = [&](int buf, const u32x4 (&r)[6]) {
     As[buf][s0] = r[0];
     As[buf][s1] = r[1];
     Bs[buf][s0] = r[2];
     Bs[buf][s1] = r[3];
+    Bs[buf][s2] = r[4];
+    Bs[buf][s3] = r[5];
   };
 
-  floatx16 acc[2][2];
+  floatx16 acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
@@ -166,21 +175,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < kStepK / 16; ++kk) {
-      bf16x8 fa[2], fb[2];
+      bf16x8 fa[2], fb[4];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const u32x4 v = As[buf][swz(wr + 32 * i + frow, 2 * kk + fh)];
         fa[i] = __builtin_bit_cast(bf16x8, v);
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < 4; ++j) {
         const u32x4 v = Bs[buf][swz(wc + 32 * j + frow, 2 * kk + fh)];
         fb[j] = __builtin_bit_cast(bf16x8, v);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
   };
 
@@ -209,7 +218,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   if constexpr (DUMP) {
     // the accumulators themselves, for a check of the error bound
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < 4; ++j) {
       const int64_t b = b0 + wc + 32 * j + (lane & 31);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -225,7 +234,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // epilogue: threshold test and compaction by wave ballot
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < 4; ++j) {
     const int64_t b = b0 + wc + 32 * j + (lane & 31);
     const float nb = a.nh[b];
     const int32_t ib = a.sid[b];
@@ -236,7 +245,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int64_t ar = a0 + wr + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const float na = a.nh[ar];
         const float p = na * nb;
-        const bool want = (I < J || ar < b) && p * (1.0f + 0x1p-20f) >= a.t &&
+        // the upper triangle only: a tile reaching the diagonal also holds
+        // pairs (b, a) of earlier rows, and rows pair with themselves
+        const bool want = ar < b && p * (1.0f + 0x1p-20f) >= a.t &&
                           acc[i][j][r] >= a.t - kScreenMargin * p - kScreenEps;
         const uint64_t m = __ballot(want);
         if (m) {

@@ -37,11 +37,11 @@ extern "C" int apss_probe_screen_products(apss_index* ix, const int32_t* rows, i
   hipStream_t s = ix->ws.stream;
   const int32_t head = sx->head_cut;
   const int32_t ld = (head + kScreenK - 1) / kScreenK * kScreenK;
-  const int64_t Sp = (S + kScreenTile - 1) / kScreenTile * kScreenTile;
-  const int64_t T = Sp / kScreenTile;
+  const int64_t Sp = (S + kScreenTileB - 1) / kScreenTileB * kScreenTileB;
+  const int64_t T = Sp / kScreenTile, TB = Sp / kScreenTileB;
   std::vector<int32_t> tl;
   for (int64_t I = 0; I < T; ++I)
-    for (int64_t J = I; J < T; ++J) {
+    for (int64_t J = I / 2; J < TB; ++J) {
       tl.push_back((int32_t)I);
       tl.push_back((int32_t)J);
     }
