@@ -81,6 +81,20 @@ def test_screened_range_groups(apss):
         assert_identical(plain, scr)
 
 
+@pytest.mark.parametrize("variant,range_rows,sd,rg", [(2, 16384, 4096, 1), (1, 8192, 4096, 1), (2, 4096, 1024, 1),
+                                                    (1, 4096, 1024, 2)])
+def test_sparse_pass_wide_ranges(apss, variant, range_rows, sd, rg):
+    # geometries where many ranges of the sparse pass hold more entries than
+    # the hash table takes and go block by block, beside ranges that fit it:
+    # the plain join's pairs bit for bit
+    V = make_corpus(spec_for("c4", n=20000))
+    t = 0.8
+    plain = join(apss, V, t)
+    scr = join(apss, V, t, screen_dims=sd, variant=variant, range_rows=range_rows, range_group=rg)
+    assert_identical(plain, scr)
+    assert_parity(scr[0], scr[1], scr[2], oracle.join_plain(V, np.float32(t)), float(np.float32(t)), V)
+
+
 def test_screen_finds_pairs_with_no_tail_overlap(apss):
     """Near-duplicate rows that live almost entirely in the head: the
     matches must come from the MFMA screen (the sparse pass cannot see them)."""
