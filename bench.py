@@ -566,8 +566,8 @@ def main():
     value = cand / (ms_step / 1000.0)
     # algorithmic bytes of the candidate kernel: the 4-byte packed list entry
     # it streams per posting visit, 8 B per query component read, 12 B per
-    # emitted pair.  (The survey's convention counts 8 B per visit, an id and
-    # a float weight; that figure is reported beside it.)
+    # emitted pair.  (A convention that prices a visit at an unpacked posting
+    # counts 8 B, an id and a float weight; that figure is reported beside it.)
     alg_bytes = 4.0 * stats["posting_visits"] + 8.0 * V.nnz + 12.0 * stats["matches"]
     alg_bytes_8b = alg_bytes + 4.0 * stats["posting_visits"]
     kms = sum(kern_ms) / len(kern_ms)
